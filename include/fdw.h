@@ -1,0 +1,183 @@
+/*
+ * fdw.h - C-ABI of the MI355X (gfx950) explicit leapfrog solver for the regularised
+ * tsunami wave equation of arXiv 2005.11931,
+ *
+ *     u_tt = d_x(h1(x,y) d_x u) + d_y(h2(x,y) d_y u),  (t,x,y) in [0,T] x [x0,x1] x [y0,y1],
+ *     u(0) = u0,  u_t(0) = u1,  u = 0 on the boundary,
+ *
+ * i.e. the Cauchy problem of Section 2, equation (2.1) with the vector-valued coefficient
+ * h = (h1, h2) (positive, Section 2), regularised by mollification (Section 2.1,
+ * Section 3.1), on the node grid and with the zero Dirichlet data of Section 3.3.
+ *
+ * Discretisation (the paper's own solvers are implicit; this library is explicit):
+ *   face coefficients  hx_{i+1/2,j} = (h1_{i,j} + h1_{i+1,j})/2,  hy_{i,j+1/2} likewise with h2;
+ *   operator           (A u)_ij = [hx_{i+1/2}(u_{i+1}-u_i) + hx_{i-1/2}(u_{i-1}-u_i)]/dx^2 + (same in y)/dy^2;
+ *   start              u^1 = u^0 + tau u1 + (tau^2/2) A u^0;
+ *   leapfrog           u^{n+1} = 2 u^n - u^{n-1} + tau^2 A u^n;
+ *   energy             E^{n+1/2} = dx dy [ sum ((u^{n+1}-u^n)/tau)^2 + <K u^{n+1}, u^n> ],  K = -A,
+ *                      the discrete form of the conservation law of Section 2 (proof of
+ *                      Theorem 2.1, identity CL-01), constant in exact arithmetic.
+ * The state is carried in increment form (u^n, du^n = u^n - u^{n-1}), which is the same
+ * recurrence in exact arithmetic and keeps the velocity information that FP32 would lose
+ * in 2u^n - u^{n-1} when tau is small.
+ *
+ * Conventions for every entry point:
+ *   - all arrays are row-major [ny][nx] (x fastest), dense, in the problem's storage type
+ *     (float for FDW_F32, double for FDW_F64) unless stated as double;
+ *   - "device" pointers are HIP device memory on the current device; "host" pointers are
+ *     ordinary host memory;
+ *   - the caller owns every pointer it passes, including the workspace; inputs are copied
+ *     (stream-ordered) during the call, so they may be reused once the stream reaches it;
+ *   - work is enqueued on the stream given to fdw_init (hipStream_t passed as void*, NULL
+ *     for the null stream); calls return before the GPU finishes unless stated otherwise;
+ *   - every entry point returns FDW_OK (0) or a negative FDW_E* code and never aborts;
+ *     fdw_last_error() gives a one-line description of the last failure on that context;
+ *   - a context is not thread-safe; separate contexts are independent.
+ */
+#ifndef FDW_H
+#define FDW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdw_ctx fdw_ctx; /* opaque */
+
+typedef enum { FDW_F32 = 0, FDW_F64 = 1 } fdw_dtype;
+
+enum {
+    FDW_OK = 0,
+    FDW_EINVAL = -1,    /* bad argument: sizes, tau <= 0, T/tau not an integer, NULL pointer,
+                           non-finite or negative h, receiver outside the interior */
+    FDW_ECFL = -2,      /* tau^2 (4 max hx/dx^2 + 4 max hy/dy^2) > 4: leapfrog would be unstable */
+    FDW_ESTATE = -3,    /* call out of order (e.g. stepping before fdw_set_coeff) */
+    FDW_ENOMEM = -4,    /* workspace too small */
+    FDW_EHIP = -5,      /* a HIP runtime error; see fdw_last_error */
+    FDW_EUNSTABLE = -6, /* a non-finite energy was produced */
+    FDW_ENOTSUP = -7    /* configuration not supported */
+};
+
+/* fdw_problem.flags */
+enum {
+    FDW_ALLOW_UNSTABLE = 1u, /* skip the stability (CFL) check in fdw_set_coeff */
+    FDW_ALLOW_ZERO_H = 2u    /* accept h >= 0 instead of h > 0 (e.g. h2 = 0 decouples rows into 1D problems) */
+};
+
+/* One regularised problem (Section 2, eq. (2.1); grid of Section 3.3).
+ * nx, ny >= 3 nodes including the boundary ring; dx = (x1-x0)/(nx-1), dy = (y1-y0)/(ny-1);
+ * tau > 0; N = llround(T/tau) steps with |N tau - T| <= 1e-9 T (T = 0 allowed: N = 0). */
+typedef struct {
+    int32_t nx, ny;
+    double x0, x1, y0, y1;
+    double tau, T;
+    int32_t dtype; /* fdw_dtype */
+    uint32_t flags;
+} fdw_problem;
+
+/* Device workspace (bytes) that fdw_init needs for `count` members described by
+ * problems[0..count-1].  Returns 0 when the problems are invalid. */
+size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count);
+
+/* Create a context for `count` >= 1 members (count > 1 is a batched family: members may
+ * differ in size, tau and coefficient but share the storage type).
+ * workspace: device memory of ws_bytes >= fdw_workspace_bytes(), 256-byte aligned, owned by
+ *            the caller and alive until fdw_destroy;
+ * u0, u1:    arrays of `count` device pointers, member m's initial displacement and
+ *            velocity, [ny_m][nx_m] in the storage type (the boundary ring is taken as 0);
+ * hip_stream: hipStream_t the context enqueues on (NULL = null stream).
+ * On success *out receives the context at step n = 0. */
+int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t ws_bytes,
+             const void* const* u0, const void* const* u1, void* hip_stream, fdw_ctx** out);
+
+/* Set member m's coefficient (a1: face coefficients and the stability check).
+ * h1: device [ny][nx] nodal h1; h2: device nodal h2, or NULL when h2 = h1 (the physical
+ * model h_1 = h_2 = h; a faster nodal layout is used).  The values are validated (finite,
+ * > 0, or >= 0 with FDW_ALLOW_ZERO_H) and the CFL bound is checked; both read one small
+ * result back to the host, so this call synchronises the stream.  Resets member m to n = 0. */
+int fdw_set_coeff(fdw_ctx* ctx, int32_t member, const void* h1, const void* h2);
+
+/* Advance every member by n >= 0 steps (a2 start step when a member is at n = 0, then a3
+ * leapfrog steps).  energy_dev: NULL, or device double [count][n] receiving
+ * E^{k+1/2} for k = n_cur .. n_cur+n-1 of each member (a5).  Traces registered with
+ * fdw_record_traces are written as the steps are taken (a7). */
+int fdw_step_n(fdw_ctx* ctx, int64_t n, double* energy_dev);
+
+/* E^{n-1/2} of each member's current pair (u^{n-1}, u^n), into host double [count].
+ * Needs n >= 1 (FDW_ESTATE otherwise); synchronises the stream. */
+int fdw_energy(fdw_ctx* ctx, double* energy_host);
+
+/* Record traces of member m: from now on u^k at the R receivers is written into
+ * traces[k][r] (device, storage type, [N+1][R], N = the member's llround(T/tau)) for every
+ * step k <= N taken; the current step's row is written immediately.
+ * recv_ij: device int32 [R][2] = (i, j) of interior nodes, copied during the call.
+ * R = 0 (or traces = NULL) stops recording. */
+int fdw_record_traces(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, void* traces);
+
+/* Misfit of a7: J = sum_{k=0}^{rows-1} sum_r (traces[k][r] - d[k][r])^2 in double, and the
+ * adjoint source trace_grad[k][r] = 2 (traces - d) (double, may be NULL).  traces is in the
+ * storage type of member m, d is double; all device; J_dev is a device double. */
+int fdw_misfit(fdw_ctx* ctx, int32_t member, const void* traces, const double* d, int64_t rows, int32_t R,
+               double* J_dev, double* trace_grad);
+
+/* Device workspace (bytes) fdw_adjoint needs for member m with checkpoints every
+ * ckpt_every steps (a9). */
+size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t ckpt_every);
+
+/* Gradient with respect to the nodal coefficient(s) of a loss L of the traces u^k_r,
+ * k = 0..N (a8, a9): the forward recurrence is replayed from member m's initial data
+ * storing the state every ckpt_every steps, then the transposed (reverse leapfrog)
+ * recurrence runs backwards, each segment being reconstructed from its checkpoint by time
+ * reversal.  trace_grad: device double [N+1][R] = dL/du^k at the receivers;
+ * recv_ij: device int32 [R][2] (interior nodes); adj_ws: device workspace of
+ * fdw_adjoint_workspace_bytes() bytes; grad_h1: device double [ny][nx] receives dL/dh1;
+ * grad_h2: device double [ny][nx] receives dL/dh2, or NULL to receive dL/dh1 + dL/dh2 in
+ * grad_h1 (the case h1 = h2 = h).  The forward state of the context is left unchanged. */
+int fdw_adjoint(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, const double* trace_grad,
+                int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes, double* grad_h1, double* grad_h2);
+
+/* Snapshot / resume (a6): copy member m's state (u^n, du^n = u^n - u^{n-1}) to device
+ * buffers [ny][nx] in the storage type and its step counter to *n (host).  du is all zeros
+ * at n = 0.  u and du may be NULL. */
+int fdw_get_state(fdw_ctx* ctx, int32_t member, void* u, void* du, int64_t* n);
+
+/* Overwrite member m's state with (u^n, du^n) from device buffers and set its step counter.
+ * n >= 1 (at n = 0 the state is defined by the initial data). */
+int fdw_set_state(fdw_ctx* ctx, int32_t member, const void* u, const void* du, int64_t n);
+
+/* Return member m to step 0 (its initial data). */
+int fdw_reset(fdw_ctx* ctx, int32_t member);
+
+/* Step counter of member m, or -1 on a bad argument. */
+int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
+
+/* Execution configuration (tuning; results do not depend on it, bit for bit):
+ *   FDW_CFG_TIME_BLOCK: time steps per stencil launch, 1..8 (0 = automatic);
+ *   FDW_CFG_SEGMENT_ROWS: rows per streaming work item, 8..4096 (0 = automatic);
+ *   FDW_CFG_USE_GRAPH: 1 captures the launch sequence of a step_n call in a hipGraph and
+ *     replays it for later calls with the same shape (0 = plain launches);
+ *   FDW_CFG_BATCH_MODE: for count > 1, 0 = one launch per time block covering all members,
+ *     1 = one persistent cooperative launch per step_n call. */
+enum { FDW_CFG_TIME_BLOCK = 1, FDW_CFG_SEGMENT_ROWS = 2, FDW_CFG_USE_GRAPH = 3, FDW_CFG_BATCH_MODE = 4 };
+int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
+int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
+
+/* Autotune the execution configuration for this context: times short runs of the candidate
+ * (time block, segment rows) pairs on the context's stream, picks the fastest (ties go to
+ * the smaller time block) and applies it.  The member states are saved and restored.
+ * The choice is cached in the file named by the FDW_AUTOTUNE_CACHE environment variable
+ * (if set) under a key of (device arch, storage type, nx, ny, layout, count).
+ * steps: time steps per candidate run (0 = automatic).  best_out (host, may be NULL)
+ * receives {time_block, segment_rows}. */
+int fdw_autotune(fdw_ctx* ctx, int32_t steps, int64_t* best_out);
+
+const char* fdw_last_error(const fdw_ctx* ctx);
+const char* fdw_status_string(int status);
+void fdw_destroy(fdw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1206 @@
+// fdw_api.hip - host side of libfdw: validation, workspace carving, the member table, the
+// launch sequence of a step_n call (optionally captured in a hipGraph), snapshots and the
+// autotuner.  The problem it solves is the regularised Cauchy problem of arXiv 2005.11931,
+// Section 2 eq. (2.1), on the grid of Section 3.3 (see include/fdw.h).
+#include "../../include/fdw.h"
+#include "fdw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace fdw;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int cols_per_lane(int dtype) { return dtype == FDW_F32 ? 4 : 2; }
+inline size_t elem_size(int dtype) { return dtype == FDW_F32 ? 4 : 8; }
+inline int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }
+constexpr int kMinSegRows = 16;
+
+struct HostMember {
+    fdw_problem p;
+    int nx = 0, ny = 0, ld = 0;
+    int64_t N = 0;
+    double dx = 0, dy = 0, tau = 0;
+    int face = 0;
+    bool coeff = false;
+    int64_t n = 0;  // steps taken
+    int cur = 0;    // pair holding the state (n >= 1)
+    void* u[2] = {nullptr, nullptr};
+    void* d[2] = {nullptr, nullptr};
+    void* h = nullptr;
+    void* hy = nullptr;
+    void* u0 = nullptr;
+    void* u1 = nullptr;
+    int* rec_ij = nullptr;
+    int* rowptr = nullptr;
+    int* rcol = nullptr;
+    int* rid = nullptr;
+    double* epart = nullptr;
+    int epart_stride = 0;
+    int R = 0;
+    void* traces = nullptr;
+    size_t plane_bytes = 0;
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct fdw_ctx {
+    int count = 0;
+    int dtype = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+    std::vector<HostMember> m;
+    std::vector<MemberDev> tab;  // host mirror of the device table
+    MemberDev* tab_dev = nullptr;
+    double* red = nullptr;
+    int* status = nullptr;
+    int* barrier = nullptr;
+    double* scal = nullptr;  // small device scalars (energies read back by fdw_energy)
+    int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0;
+    int S_eff = 0;
+    int64_t ctx_step = 0;
+    int64_t launches = 0;
+    std::map<std::tuple<int64_t, int, const double*, int, int>, GraphEntry> graphs;
+};
+
+namespace {
+
+int fail(fdw_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                             \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail((ctx), FDW_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+bool problem_ok(const fdw_problem& p, std::string* why, int64_t* N_out)
+{
+    if (p.nx < 3 || p.ny < 3) return *why = "nx and ny must be >= 3", false;
+    if ((int64_t)p.nx * p.ny > (int64_t)1 << 31) return *why = "grid too large", false;
+    if (!(p.x1 > p.x0) || !(p.y1 > p.y0) || !std::isfinite(p.x0) || !std::isfinite(p.x1) || !std::isfinite(p.y0) ||
+        !std::isfinite(p.y1))
+        return *why = "domain must satisfy x0 < x1, y0 < y1 (finite)", false;
+    if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return *why = "tau must be finite and > 0", false;
+    if (!(p.T >= 0.0) || !std::isfinite(p.T)) return *why = "T must be finite and >= 0", false;
+    if (p.dtype != FDW_F32 && p.dtype != FDW_F64) return *why = "dtype must be FDW_F32 or FDW_F64", false;
+    const double q = p.T / p.tau;
+    const int64_t N = (int64_t)std::llround(q);
+    if (std::fabs((double)N * p.tau - p.T) > 1e-9 * std::max(p.T, p.tau)) return *why = "T/tau is not an integer", false;
+    if (N_out) *N_out = N;
+    return true;
+}
+
+int max_strips(int nx, int C)
+{
+    const int Hx = ((kMaxTimeBlock + C - 1) / C) * C;
+    const int Wv = kWaveSize * C - 2 * Hx;
+    return (nx + Wv - 1) / Wv;
+}
+
+size_t member_bytes(const fdw_problem& p)
+{
+    const int ld = pitch_of(p.nx);
+    const size_t plane = align_up((size_t)ld * p.ny * elem_size(p.dtype), kAlign);
+    const int C = cols_per_lane(p.dtype);
+    const size_t maxw = (size_t)max_strips(p.nx, C) * (size_t)((p.ny + kMinSegRows - 1) / kMinSegRows);
+    size_t b = 8 * plane;                                          // u[2], d[2], h, hy, u0, u1
+    b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);        // rec_ij
+    b += align_up(sizeof(int) * (size_t)(p.ny + 1), kAlign);       // rowptr
+    b += 2 * align_up(sizeof(int) * kMaxReceivers, kAlign);        // col, id
+    b += align_up(sizeof(double) * kMaxTimeBlock * maxw, kAlign);  // energy partials
+    return b;
+}
+
+size_t header_bytes(int count)
+{
+    size_t b = align_up(sizeof(MemberDev) * (size_t)count, kAlign);
+    b += align_up(sizeof(double) * (4 * kRedBlocks + 16), kAlign);  // red
+    b += align_up(sizeof(int) * 16, kAlign);                         // status
+    b += align_up(sizeof(int) * 16, kAlign);                         // barrier
+    b += align_up(sizeof(double) * (size_t)std::max(count, 1) * 2, kAlign);  // scalars
+    return b;
+}
+
+void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int K)
+{
+    const int C = cols_per_lane(c->dtype);
+    const int Hx = ((K + C - 1) / C) * C;
+    const int Wv = kWaveSize * C - 2 * Hx;
+    md.seg_rows = S;
+    md.segs = (hm.ny + S - 1) / S;
+    md.strips = (hm.nx + Wv - 1) / Wv;
+    md.waves = md.strips * md.segs;
+    md.blocks = (md.waves + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
+int choose_K(const fdw_ctx* c)
+{
+    if (c->K_cfg > 0) return c->K_cfg;
+    return c->dtype == FDW_F32 ? 4 : 2;
+}
+
+int choose_S(const fdw_ctx* c)
+{
+    if (c->S_cfg > 0) return c->S_cfg;
+    // Aim at about 2048 streaming waves (2 per SIMD) for the largest member, with segments
+    // of at least 64 rows so that the 2K-row pipeline fill stays a small fraction.
+    int best = 64;
+    for (const HostMember& hm : c->m) {
+        const int C = cols_per_lane(c->dtype);
+        const int strips = max_strips(hm.nx, C);
+        int64_t want = ((int64_t)hm.ny * strips + 2047) / 2048;
+        int S = (int)std::max<int64_t>(64, want);
+        S = (S + 7) / 8 * 8;
+        best = std::max(best, std::min(S, (int)align_up((size_t)hm.ny, 8)));
+    }
+    return best;
+}
+
+__global__ void k_write_member(MemberDev* tab, int m, MemberDev val) { tab[m] = val; }
+
+int push_member(fdw_ctx* c, int m, hipStream_t s = nullptr)
+{
+    hipLaunchKernelGGL(k_write_member, dim3(1), dim3(1), 0, s ? s : c->stream, c->tab_dev, m, c->tab[m]);
+    HIPCHK(c, hipGetLastError());
+    return FDW_OK;
+}
+
+// Rebuild the launch decomposition for time block K (all members) and push the table.
+int layout_for_K(fdw_ctx* c, int K, int S, hipStream_t st = nullptr)
+{
+    int base = 0;
+    for (int i = 0; i < c->count; ++i) {
+        MemberDev& md = c->tab[i];
+        decompose(c, c->m[i], md, S, K);
+        md.block_base = base;
+        base += md.blocks;
+    }
+    for (int i = 0; i < c->count; ++i) {
+        int rc = push_member(c, i, st);
+        if (rc) return rc;
+    }
+    return FDW_OK;
+}
+
+void sync_member_dev(fdw_ctx* c, int i)
+{
+    HostMember& hm = c->m[i];
+    MemberDev& md = c->tab[i];
+    md.cur0 = hm.cur ^ (int)(c->launches & 1);
+    md.n_offset = hm.n - c->ctx_step;
+    md.face = hm.face;
+    md.R = hm.R;
+    md.traces = hm.traces;
+}
+
+template <typename T>
+int do_start(fdw_ctx* c, int i, double* energy_out)
+{
+    HostMember& hm = c->m[i];
+    MemberDev& md = c->tab[i];
+    HIPCHK(c, launch_start<T>(&md, c->tab_dev + i, hm.u0, hm.u1, (T)hm.tau, energy_out != nullptr, 0, energy_out,
+                              c->red, c->stream));
+    hm.n = 1;
+    hm.cur = 0;
+    if (hm.R > 0 && hm.traces && 1 < hm.N + 1)
+        HIPCHK(c, launch_gather<T>(hm.u[0], hm.ld, hm.rec_ij, hm.R, (char*)hm.traces + (size_t)hm.R * sizeof(T),
+                                   c->stream));
+    return FDW_OK;
+}
+
+// One streaming launch of K steps over members [first, first + nm) (all members when nm == count).
+template <typename T>
+int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, hipStream_t s)
+{
+    StepArgs a;
+    a.table = c->tab_dev;
+    a.first = first;
+    a.nmembers = nm;
+    a.block_offset = c->tab[first].block_base;
+    int total = 0;
+    for (int i = first; i < first + nm; ++i) total += c->tab[i].blocks;
+    a.total_blocks = total;
+    a.parity = (int)(c->launches & 1);
+    a.want_energy = energy ? 1 : 0;
+    a.want_trace = trace ? 1 : 0;
+    a.ctx_step = c->ctx_step;
+    int face_mode = c->m[first].face;
+    for (int i = first; i < first + nm; ++i)
+        if (c->m[i].face != face_mode) face_mode = -1;
+    if (face_mode < 0) {
+        // mixed layouts in one batch: launch per member
+        for (int i = first; i < first + nm; ++i) {
+            a.first = i;
+            a.nmembers = 1;
+            a.block_offset = c->tab[i].block_base;
+            a.total_blocks = c->tab[i].blocks;
+            HIPCHK(c, launch_step<T>(a, K, c->m[i].face, a.total_blocks, s));
+        }
+        return FDW_OK;
+    }
+    HIPCHK(c, launch_step<T>(a, K, face_mode, total, s));
+    return FDW_OK;
+}
+
+bool any_trace(const fdw_ctx* c)
+{
+    for (const HostMember& hm : c->m)
+        if (hm.R > 0 && hm.traces) return true;
+    return false;
+}
+
+// The main loop of step_n once every member is in lock-step: `steps` steps, energies of the
+// first of them land at energy_dev[m * stride + koff + ...].
+template <typename T>
+int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, int64_t koff, hipStream_t s)
+{
+    const int K = choose_K(c);
+    const bool trace = any_trace(c);
+    int64_t left = steps, k = koff;
+    int curK = -1;
+    while (left > 0) {
+        const int Kb = (int)std::min<int64_t>(K, left);
+        if (Kb != curK) {
+            int rc = layout_for_K(c, Kb, c->S_eff, s);
+            if (rc) return rc;
+            curK = Kb;
+        }
+        int rc = launch_block<T>(c, 0, c->count, Kb, energy_dev != nullptr, trace, s);
+        if (rc) return rc;
+        if (energy_dev)
+            HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, Kb, energy_dev, stride, k, s));
+        c->ctx_step += Kb;
+        c->launches += 1;
+        for (HostMember& hm : c->m) {
+            hm.n += Kb;
+            hm.cur ^= 1;
+        }
+        left -= Kb;
+        k += Kb;
+    }
+    if (curK != K) {
+        // leave the table in the main configuration
+        int rc = layout_for_K(c, K, c->S_eff, s);
+        if (rc) return rc;
+    }
+    return FDW_OK;
+}
+
+template <typename T>
+int run_persistent(fdw_ctx* c, int64_t steps)
+{
+    const int Kc = choose_K(c);
+    const int K = Kc >= 4 ? 4 : (Kc >= 2 ? 2 : 1);
+    int face_mode = c->m[0].face;
+    for (const HostMember& hm : c->m)
+        if (hm.face != face_mode) return fail(c, FDW_ENOTSUP, "persistent batch needs one coefficient layout");
+    int rc = layout_for_K(c, K, c->S_eff);
+    if (rc) return rc;
+    const int64_t phases = steps / K;
+    const int64_t tail = steps - phases * K;
+    int total = 0;
+    for (const MemberDev& md : c->tab) total += md.blocks;
+    int grid = std::min(total, persistent_max_blocks<T>(K, face_mode));
+    if (grid < 1) return fail(c, FDW_EHIP, "persistent launch: no resident blocks");
+    if (phases > 0) {
+        HIPCHK(c, launch_fill_bytes(c->barrier, 16 * sizeof(int), c->stream));
+        StepArgs a;
+        a.table = c->tab_dev;
+        a.first = 0;
+        a.nmembers = c->count;
+        a.block_offset = 0;
+        a.total_blocks = total;
+        a.parity = (int)(c->launches & 1);
+        a.want_energy = 0;
+        a.want_trace = 0;
+        a.ctx_step = c->ctx_step;
+        if (phases > INT32_MAX) return fail(c, FDW_EINVAL, "too many steps for one persistent launch");
+        HIPCHK(c, launch_step_persistent<T>(a, K, face_mode, (int)phases, grid, c->barrier, c->stream));
+        c->ctx_step += phases * K;
+        c->launches += phases;
+        for (HostMember& hm : c->m) {
+            hm.n += phases * K;
+            if (phases & 1) hm.cur ^= 1;
+        }
+    }
+    if (tail > 0) return run_blocks<T>(c, tail, nullptr, 0, 0, c->stream);
+    return FDW_OK;
+}
+
+template <typename T>
+int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
+{
+    for (int i = 0; i < c->count; ++i)
+        if (!c->m[i].coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff has not been called for member " + std::to_string(i));
+    if (n == 0) return FDW_OK;
+    bool any0 = false, any1 = false;
+    for (const HostMember& hm : c->m) (hm.n == 0 ? any0 : any1) = true;
+    int64_t done = 0;
+    if (any0 || any1) {
+        if (any0) {
+            // members at n = 0 take the start step; the others one single-member step, so that
+            // all are in lock-step afterwards
+            for (int i = 0; i < c->count; ++i) {
+                HostMember& hm = c->m[i];
+                double* e = energy_dev ? energy_dev + (int64_t)i * n : nullptr;
+                if (hm.n == 0) {
+                    int rc = do_start<T>(c, i, e);
+                    if (rc) return rc;
+                } else {
+                    int rc = layout_for_K(c, 1, c->S_eff);
+                    if (rc) return rc;
+                    rc = launch_block<T>(c, i, 1, 1, e != nullptr, any_trace(c), c->stream);
+                    if (rc) return rc;
+                    if (e) HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, i, 1, 1, energy_dev, n, 0, c->stream));
+                    // this member alone advanced: its parity and offset move relative to the context
+                    hm.n += 1;
+                    hm.cur ^= 1;
+                }
+            }
+            done = 1;
+            for (int i = 0; i < c->count; ++i) sync_member_dev(c, i);
+            int rc = layout_for_K(c, choose_K(c), c->S_eff);
+            if (rc) return rc;
+        }
+    }
+    const int64_t left = n - done;
+    if (left <= 0) return FDW_OK;
+    if (c->batch_mode == 1 && energy_dev == nullptr && !any_trace(c)) return run_persistent<T>(c, left);
+    if (c->use_graph && !any_trace(c)) {
+        // The launch sequence of the main loop depends only on (steps, K, energy pointer and
+        // offset, launch parity); capture it once and replay it.
+        const auto key = std::make_tuple(left, choose_K(c), (const double*)energy_dev, (int)(c->launches & 1),
+                                         (int)done);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = run_blocks<T>(c, left, energy_dev, n, done, c->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(c, FDW_EHIP, std::string("capture: ") + hipGetErrorString(e));
+            GraphEntry ge;
+            e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(c, FDW_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+            it = c->graphs.emplace(key, ge).first;
+        } else {
+            // replay: the same bookkeeping as run_blocks
+            const int K = choose_K(c);
+            int64_t l = left;
+            while (l > 0) {
+                const int Kb = (int)std::min<int64_t>(K, l);
+                c->ctx_step += Kb;
+                c->launches += 1;
+                for (HostMember& hm : c->m) {
+                    hm.n += Kb;
+                    hm.cur ^= 1;
+                }
+                l -= Kb;
+            }
+        }
+        HIPCHK(c, hipGraphLaunch(it->second.exec, c->stream));
+        return FDW_OK;
+    }
+    return run_blocks<T>(c, left, energy_dev, n, done, c->stream);
+}
+
+}  // namespace
+
+// =============================================================================================
+// C-ABI
+// =============================================================================================
+extern "C" {
+
+const char* fdw_status_string(int s)
+{
+    switch (s) {
+    case FDW_OK: return "ok";
+    case FDW_EINVAL: return "invalid argument";
+    case FDW_ECFL: return "time step above the stability bound";
+    case FDW_ESTATE: return "call out of order";
+    case FDW_ENOMEM: return "workspace too small";
+    case FDW_EHIP: return "HIP runtime error";
+    case FDW_EUNSTABLE: return "non-finite energy";
+    case FDW_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+const char* fdw_last_error(const fdw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count)
+{
+    if (!problems || count < 1) return 0;
+    size_t b = header_bytes(count);
+    std::string why;
+    for (int i = 0; i < count; ++i) {
+        if (!problem_ok(problems[i], &why, nullptr)) return 0;
+        if (problems[i].dtype != problems[0].dtype) return 0;
+        b += member_bytes(problems[i]);
+    }
+    return b;
+}
+
+int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t ws_bytes, const void* const* u0,
+             const void* const* u1, void* hip_stream, fdw_ctx** out)
+{
+    if (!out) return FDW_EINVAL;
+    *out = nullptr;
+    if (!problems || count < 1 || !workspace || !u0 || !u1) return FDW_EINVAL;
+    if (((uintptr_t)workspace) % kAlign) return FDW_EINVAL;
+    std::string why;
+    for (int i = 0; i < count; ++i) {
+        if (!problem_ok(problems[i], &why, nullptr)) return FDW_EINVAL;
+        if (problems[i].dtype != problems[0].dtype) return FDW_EINVAL;
+        if (!u0[i] || !u1[i]) return FDW_EINVAL;
+    }
+    const size_t need = fdw_workspace_bytes(problems, count);
+    if (need == 0) return FDW_EINVAL;
+    if (ws_bytes < need) return FDW_ENOMEM;
+
+    fdw_ctx* c = new fdw_ctx();
+    c->count = count;
+    c->dtype = problems[0].dtype;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return FDW_EHIP;
+    }
+    char* w = (char*)workspace;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = w + off;
+        off += align_up(bytes, kAlign);
+        return (void*)p;
+    };
+    c->tab_dev = (MemberDev*)take(sizeof(MemberDev) * (size_t)count);
+    c->red = (double*)take(sizeof(double) * (4 * kRedBlocks + 16));
+    c->status = (int*)take(sizeof(int) * 16);
+    c->barrier = (int*)take(sizeof(int) * 16);
+    c->scal = (double*)take(sizeof(double) * (size_t)std::max(count, 1) * 2);
+    c->m.resize(count);
+    c->tab.resize(count);
+    for (int i = 0; i < count; ++i) {
+        HostMember& hm = c->m[i];
+        const fdw_problem& p = problems[i];
+        hm.p = p;
+        hm.nx = p.nx;
+        hm.ny = p.ny;
+        hm.ld = pitch_of(p.nx);
+        problem_ok(p, &why, &hm.N);
+        hm.dx = (p.x1 - p.x0) / (p.nx - 1);
+        hm.dy = (p.y1 - p.y0) / (p.ny - 1);
+        hm.tau = p.tau;
+        hm.plane_bytes = align_up((size_t)hm.ld * p.ny * elem_size(c->dtype), kAlign);
+        for (int k = 0; k < 2; ++k) hm.u[k] = take(hm.plane_bytes);
+        for (int k = 0; k < 2; ++k) hm.d[k] = take(hm.plane_bytes);
+        hm.h = take(hm.plane_bytes);
+        hm.hy = take(hm.plane_bytes);
+        hm.u0 = take(hm.plane_bytes);
+        hm.u1 = take(hm.plane_bytes);
+        hm.rec_ij = (int*)take(sizeof(int) * 2 * kMaxReceivers);
+        hm.rowptr = (int*)take(sizeof(int) * (size_t)(p.ny + 1));
+        hm.rcol = (int*)take(sizeof(int) * kMaxReceivers);
+        hm.rid = (int*)take(sizeof(int) * kMaxReceivers);
+        const int C = cols_per_lane(c->dtype);
+        hm.epart_stride = max_strips(p.nx, C) * ((p.ny + kMinSegRows - 1) / kMinSegRows);
+        hm.epart = (double*)take(sizeof(double) * kMaxTimeBlock * (size_t)hm.epart_stride);
+
+        MemberDev& md = c->tab[i];
+        std::memset(&md, 0, sizeof(md));
+        md.nx = hm.nx;
+        md.ny = hm.ny;
+        md.ld = hm.ld;
+        md.trace_rows = hm.N + 1;
+        md.ax = 0.5 * p.tau * p.tau / (hm.dx * hm.dx);
+        md.ay = 0.5 * p.tau * p.tau / (hm.dy * hm.dy);
+        md.escale = hm.dx * hm.dy / (p.tau * p.tau);
+        for (int k = 0; k < 2; ++k) {
+            md.u[k] = hm.u[k];
+            md.d[k] = hm.d[k];
+        }
+        md.h = hm.h;
+        md.hy = hm.hy;
+        md.rec_rowptr = hm.rowptr;
+        md.rec_col = hm.rcol;
+        md.rec_id = hm.rid;
+        md.epart = hm.epart;
+        md.epart_stride = hm.epart_stride;
+    }
+    if (off > ws_bytes) {
+        fdw_destroy(c);
+        return FDW_ENOMEM;
+    }
+    int rc = FDW_OK;
+    // zero everything, then bring in the initial data (boundary ring zeroed)
+    if (launch_fill_bytes(workspace, off, c->stream) != hipSuccess) rc = FDW_EHIP;
+    for (int i = 0; i < count && rc == FDW_OK; ++i) {
+        HostMember& hm = c->m[i];
+        hipError_t e = (c->dtype == FDW_F32) ? launch_copy_in<float>(u0[i], hm.nx, hm.ny, hm.u0, hm.ld, 1, c->stream)
+                                             : launch_copy_in<double>(u0[i], hm.nx, hm.ny, hm.u0, hm.ld, 1, c->stream);
+        if (e == hipSuccess)
+            e = (c->dtype == FDW_F32) ? launch_copy_in<float>(u1[i], hm.nx, hm.ny, hm.u1, hm.ld, 1, c->stream)
+                                      : launch_copy_in<double>(u1[i], hm.nx, hm.ny, hm.u1, hm.ld, 1, c->stream);
+        if (e != hipSuccess) rc = FDW_EHIP;
+    }
+    if (rc == FDW_OK) {
+        c->S_eff = choose_S(c);
+        for (int i = 0; i < count; ++i) sync_member_dev(c, i);
+        rc = layout_for_K(c, choose_K(c), c->S_eff);
+    }
+    if (rc != FDW_OK) {
+        fdw_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return FDW_OK;
+}
+
+void fdw_destroy(fdw_ctx* c)
+{
+    if (!c) return;
+    for (auto& kv : c->graphs)
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+static int check_member(fdw_ctx* c, int32_t m)
+{
+    if (!c) return FDW_EINVAL;
+    if (m < 0 || m >= c->count) return fail(c, FDW_EINVAL, "member index out of range");
+    return FDW_OK;
+}
+
+static void invalidate_graphs(fdw_ctx* c)
+{
+    for (auto& kv : c->graphs)
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    c->graphs.clear();
+}
+
+int fdw_set_coeff(fdw_ctx* c, int32_t m, const void* h1, const void* h2)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    if (!h1) return fail(c, FDW_EINVAL, "h1 is NULL");
+    HostMember& hm = c->m[m];
+    const int face = h2 ? 1 : 0;
+    MemberDev tmp = c->tab[m];
+    tmp.face = face;
+    hipError_t e = (c->dtype == FDW_F32) ? launch_prepare_coeff<float>(&tmp, h1, h2, face, c->red, c->stream)
+                                         : launch_prepare_coeff<double>(&tmp, h1, h2, face, c->red, c->stream);
+    HIPCHK(c, e);
+    double st[4];
+    HIPCHK(c, hipMemcpyAsync(st, c->red + 4 * kRedBlocks, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hm.coeff = false;
+    if (st[3] != 0.0) return fail(c, FDW_EINVAL, "h contains non-finite values");
+    const bool allow0 = (hm.p.flags & FDW_ALLOW_ZERO_H) != 0;
+    if (allow0 ? !(st[0] >= 0.0) : !(st[0] > 0.0))
+        return fail(c, FDW_EINVAL, allow0 ? "h must be >= 0" : "h must be > 0 (set FDW_ALLOW_ZERO_H to allow 0)");
+    const double bound = hm.tau * hm.tau * (4.0 * st[1] / (hm.dx * hm.dx) + 4.0 * st[2] / (hm.dy * hm.dy));
+    if (!(hm.p.flags & FDW_ALLOW_UNSTABLE) && bound > 4.0 * (1.0 + 1e-12)) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "tau^2 (4 max hx/dx^2 + 4 max hy/dy^2) = %.6g > 4 (max hx %.6g, max hy %.6g)",
+                      bound, st[1], st[2]);
+        return fail(c, FDW_ECFL, buf);
+    }
+    hm.face = face;
+    hm.coeff = true;
+    hm.n = 0;
+    hm.cur = 0;
+    sync_member_dev(c, m);
+    invalidate_graphs(c);
+    return push_member(c, m);
+}
+
+int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
+{
+    if (!c) return FDW_EINVAL;
+    if (n < 0) return fail(c, FDW_EINVAL, "n must be >= 0");
+    return (c->dtype == FDW_F32) ? step_n_impl<float>(c, n, energy_dev) : step_n_impl<double>(c, n, energy_dev);
+}
+
+int fdw_energy(fdw_ctx* c, double* energy_host)
+{
+    if (!c || !energy_host) return FDW_EINVAL;
+    for (int i = 0; i < c->count; ++i)
+        if (c->m[i].n < 1) return fail(c, FDW_ESTATE, "energy needs at least one step");
+    for (int i = 0; i < c->count; ++i) {
+        HostMember& hm = c->m[i];
+        MemberDev md = c->tab[i];
+        hipError_t e = (c->dtype == FDW_F32) ? launch_state_energy<float>(&md, hm.cur, c->red, c->scal + i, c->stream)
+                                             : launch_state_energy<double>(&md, hm.cur, c->red, c->scal + i, c->stream);
+        HIPCHK(c, e);
+    }
+    HIPCHK(c, hipMemcpyAsync(energy_host, c->scal, sizeof(double) * c->count, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->count; ++i)
+        if (!std::isfinite(energy_host[i])) return fail(c, FDW_EUNSTABLE, "non-finite energy");
+    return FDW_OK;
+}
+
+int fdw_record_traces(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, void* traces)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    HostMember& hm = c->m[m];
+    if (R < 0 || R > kMaxReceivers) return fail(c, FDW_EINVAL, "R out of range");
+    if (R == 0 || !traces) {
+        hm.R = 0;
+        hm.traces = nullptr;
+        sync_member_dev(c, m);
+        invalidate_graphs(c);
+        return push_member(c, m);
+    }
+    if (!recv_ij) return fail(c, FDW_EINVAL, "recv_ij is NULL");
+    HIPCHK(c, hipMemcpyAsync(hm.rec_ij, recv_ij, sizeof(int) * 2 * (size_t)R, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_receivers_csr(hm.rec_ij, R, hm.nx, hm.ny, hm.rowptr, hm.rcol, hm.rid, c->status, c->stream));
+    int st = -1;
+    HIPCHK(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (st != 0) {
+        hm.R = 0;
+        hm.traces = nullptr;
+        sync_member_dev(c, m);
+        push_member(c, m);
+        return fail(c, FDW_EINVAL, "receivers must be interior nodes (1 <= i <= nx-2, 1 <= j <= ny-2)");
+    }
+    hm.R = R;
+    hm.traces = traces;
+    sync_member_dev(c, m);
+    invalidate_graphs(c);
+    rc = push_member(c, m);
+    if (rc) return rc;
+    if (hm.n <= hm.N) {
+        const void* u = (hm.n == 0) ? hm.u0 : hm.u[hm.cur];
+        const size_t es = elem_size(c->dtype);
+        void* row = (char*)traces + (size_t)hm.n * R * es;
+        HIPCHK(c, (c->dtype == FDW_F32) ? launch_gather<float>(u, hm.ld, hm.rec_ij, R, row, c->stream)
+                                        : launch_gather<double>(u, hm.ld, hm.rec_ij, R, row, c->stream));
+    }
+    return FDW_OK;
+}
+
+int fdw_misfit(fdw_ctx* c, int32_t m, const void* traces, const double* d, int64_t rows, int32_t R, double* J_dev,
+               double* trace_grad)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    if (!traces || !d || !J_dev || rows < 0 || R < 0) return fail(c, FDW_EINVAL, "bad misfit arguments");
+    const int64_t n = rows * (int64_t)R;
+    HIPCHK(c, (c->dtype == FDW_F32) ? launch_misfit<float>(traces, d, n, J_dev, trace_grad, c->red, c->stream)
+                                    : launch_misfit<double>(traces, d, n, J_dev, trace_grad, c->red, c->stream));
+    return FDW_OK;
+}
+
+int fdw_get_state(fdw_ctx* c, int32_t m, void* u, void* du, int64_t* n)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    HostMember& hm = c->m[m];
+    if (n) *n = hm.n;
+    const void* su = (hm.n == 0) ? hm.u0 : hm.u[hm.cur];
+    if (u)
+        HIPCHK(c, (c->dtype == FDW_F32) ? launch_copy_out<float>(su, hm.ld, hm.nx, hm.ny, u, c->stream)
+                                        : launch_copy_out<double>(su, hm.ld, hm.nx, hm.ny, u, c->stream));
+    if (du) {
+        if (hm.n == 0)
+            HIPCHK(c, launch_fill_bytes(du, (size_t)hm.nx * hm.ny * elem_size(c->dtype), c->stream));
+        else
+            HIPCHK(c, (c->dtype == FDW_F32) ? launch_copy_out<float>(hm.d[hm.cur], hm.ld, hm.nx, hm.ny, du, c->stream)
+                                            : launch_copy_out<double>(hm.d[hm.cur], hm.ld, hm.nx, hm.ny, du, c->stream));
+    }
+    return FDW_OK;
+}
+
+int fdw_set_state(fdw_ctx* c, int32_t m, const void* u, const void* du, int64_t n)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    if (!u || !du || n < 1) return fail(c, FDW_EINVAL, "set_state needs u, du and n >= 1");
+    HostMember& hm = c->m[m];
+    if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
+    HIPCHK(c, (c->dtype == FDW_F32) ? launch_copy_in<float>(u, hm.nx, hm.ny, hm.u[hm.cur], hm.ld, 1, c->stream)
+                                    : launch_copy_in<double>(u, hm.nx, hm.ny, hm.u[hm.cur], hm.ld, 1, c->stream));
+    HIPCHK(c, (c->dtype == FDW_F32) ? launch_copy_in<float>(du, hm.nx, hm.ny, hm.d[hm.cur], hm.ld, 1, c->stream)
+                                    : launch_copy_in<double>(du, hm.nx, hm.ny, hm.d[hm.cur], hm.ld, 1, c->stream));
+    hm.n = n;
+    sync_member_dev(c, m);
+    invalidate_graphs(c);
+    return push_member(c, m);
+}
+
+int fdw_reset(fdw_ctx* c, int32_t m)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    c->m[m].n = 0;
+    c->m[m].cur = 0;
+    sync_member_dev(c, m);
+    invalidate_graphs(c);
+    return push_member(c, m);
+}
+
+int64_t fdw_steps_taken(const fdw_ctx* c, int32_t m)
+{
+    if (!c || m < 0 || m >= c->count) return -1;
+    return c->m[m].n;
+}
+
+int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
+{
+    if (!c) return FDW_EINVAL;
+    switch (key) {
+    case FDW_CFG_TIME_BLOCK:
+        if (v < 0 || v > kMaxTimeBlock) return fail(c, FDW_EINVAL, "time block must be 0..8");
+        c->K_cfg = (int)v;
+        break;
+    case FDW_CFG_SEGMENT_ROWS:
+        if (v != 0 && (v < kMinSegRows || v > 4096)) return fail(c, FDW_EINVAL, "segment rows must be 0 or 16..4096");
+        c->S_cfg = (int)v;
+        c->S_eff = choose_S(c);
+        break;
+    case FDW_CFG_USE_GRAPH:
+        if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "use_graph must be 0 or 1");
+        c->use_graph = (int)v;
+        break;
+    case FDW_CFG_BATCH_MODE:
+        if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "batch mode must be 0 or 1");
+        c->batch_mode = (int)v;
+        break;
+    default: return fail(c, FDW_EINVAL, "unknown configuration key");
+    }
+    invalidate_graphs(c);
+    for (int i = 0; i < c->count; ++i) sync_member_dev(c, i);
+    return layout_for_K(c, choose_K(c), c->S_eff);
+}
+
+int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
+{
+    if (!c) return -1;
+    switch (key) {
+    case FDW_CFG_TIME_BLOCK: return choose_K(c);
+    case FDW_CFG_SEGMENT_ROWS: return c->S_eff;
+    case FDW_CFG_USE_GRAPH: return c->use_graph;
+    case FDW_CFG_BATCH_MODE: return c->batch_mode;
+    default: return -1;
+    }
+}
+
+}  // extern "C"
+
+// =============================================================================================
+// Adjoint driver (a8, a9)
+// =============================================================================================
+namespace {
+
+int adjoint_K(const fdw_ctx* c) { return c->dtype == FDW_F32 ? 2 : 2; }
+
+struct AdjLayout {
+    size_t plane = 0, plane64 = 0;
+    int64_t nck = 0;
+    size_t total = 0;
+};
+
+AdjLayout adj_layout(const fdw_ctx* c, const HostMember& hm, int ck)
+{
+    AdjLayout L;
+    L.plane = align_up((size_t)hm.ld * hm.ny * elem_size(c->dtype), kAlign);
+    L.plane64 = align_up((size_t)hm.ld * hm.ny * sizeof(double), kAlign);
+    L.nck = (hm.N >= 1 && ck >= 1) ? (hm.N - 1) / ck : 0;  // checkpoints at ck, 2ck, ... < N
+    size_t b = align_up(sizeof(MemberDev), kAlign);
+    b += 8 * L.plane + 2 * L.plane64;
+    b += (size_t)(2 * L.nck) * L.plane;
+    b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);
+    b += align_up(sizeof(int) * (size_t)(hm.ny + 1), kAlign);
+    b += 2 * align_up(sizeof(int) * kMaxReceivers, kAlign);
+    b += align_up(sizeof(int) * 16, kAlign);
+    L.total = b;
+    return L;
+}
+
+void adj_decompose(const fdw_ctx* c, const HostMember& hm, int K, int S, AdjArgs& a)
+{
+    const int C = cols_per_lane(c->dtype);
+    const int Hx = ((K + C - 1) / C) * C;
+    const int Wv = kWaveSize * C - 2 * Hx;
+    a.seg_rows = S;
+    a.segs = (hm.ny + S - 1) / S;
+    a.strips = (hm.nx + Wv - 1) / Wv;
+    a.waves = a.strips * a.segs;
+}
+
+template <typename T>
+int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double* tg, int ck, void* ws, size_t wsb,
+                 double* g1_out, double* g2_out)
+{
+    HostMember& hm = c->m[m];
+    const AdjLayout L = adj_layout(c, hm, ck);
+    if (wsb < L.total) return fail(c, FDW_ENOMEM, "adjoint workspace too small");
+    char* w = (char*)ws;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = w + off;
+        off += align_up(bytes, kAlign);
+        return (void*)p;
+    };
+    MemberDev* rep_dev = (MemberDev*)take(sizeof(MemberDev));
+    void* FU[2];
+    void* FD[2];
+    void* LA[2];
+    void* MU[2];
+    for (int k = 0; k < 2; ++k) FU[k] = take(L.plane);
+    for (int k = 0; k < 2; ++k) FD[k] = take(L.plane);
+    for (int k = 0; k < 2; ++k) LA[k] = take(L.plane);
+    for (int k = 0; k < 2; ++k) MU[k] = take(L.plane);
+    double* G1 = (double*)take(L.plane64);
+    double* G2 = (double*)take(L.plane64);
+    std::vector<void*> CU(L.nck), CD(L.nck);
+    for (int64_t k = 0; k < L.nck; ++k) {
+        CU[k] = take(L.plane);
+        CD[k] = take(L.plane);
+    }
+    int* rec = (int*)take(sizeof(int) * 2 * kMaxReceivers);
+    int* rowptr = (int*)take(sizeof(int) * (size_t)(hm.ny + 1));
+    int* rcol = (int*)take(sizeof(int) * kMaxReceivers);
+    int* rid = (int*)take(sizeof(int) * kMaxReceivers);
+    int* status = (int*)take(sizeof(int) * 16);
+    hipStream_t s = c->stream;
+
+    // zero the state planes (boundary ring and padding must be 0) and the accumulators
+    HIPCHK(c, launch_fill_bytes(FU[0], 8 * L.plane + 2 * L.plane64, s));
+    if (R > 0) {
+        HIPCHK(c, hipMemcpyAsync(rec, recv_ij, sizeof(int) * 2 * (size_t)R, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, launch_receivers_csr(rec, R, hm.nx, hm.ny, rowptr, rcol, rid, status, s));
+        int st = -1;
+        HIPCHK(c, hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (st != 0) return fail(c, FDW_EINVAL, "receivers must be interior nodes (1 <= i <= nx-2, 1 <= j <= ny-2)");
+    }
+    const int64_t N = hm.N;
+    if (N == 0) {
+        HIPCHK(c, launch_grad_out(G1, hm.ld, hm.nx, hm.ny, g1_out, s));
+        if (g2_out) HIPCHK(c, launch_grad_out(G2, hm.ld, hm.nx, hm.ny, g2_out, s));
+        return FDW_OK;
+    }
+
+    // ---- forward replay from the initial data, storing (u, du) every ck steps
+    MemberDev rep = c->tab[m];
+    for (int k = 0; k < 2; ++k) {
+        rep.u[k] = FU[k];
+        rep.d[k] = FD[k];
+    }
+    rep.R = 0;
+    rep.traces = nullptr;
+    rep.cur0 = 0;
+    rep.n_offset = 0;
+    rep.block_base = 0;
+    HIPCHK(c, launch_start<T>(&rep, rep_dev, hm.u0, hm.u1, (T)hm.tau, 0, 0, nullptr, c->red, s));
+    int cur = 0;
+    int64_t n = 1;
+    const int Kf = choose_K(c);
+    int pushedK = -1;
+    auto store_ckpt = [&](int64_t step) -> int {
+        const int64_t k = step / ck - 1;
+        HIPCHK(c, hipMemcpyAsync(CU[k], FU[cur], L.plane, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(CD[k], FD[cur], L.plane, hipMemcpyDeviceToDevice, s));
+        return FDW_OK;
+    };
+    if (n % ck == 0 && n < N) {
+        int rc = store_ckpt(n);
+        if (rc) return rc;
+    }
+    while (n < N) {
+        const int64_t next = std::min<int64_t>(N, (n / ck + 1) * ck);
+        const int Kb = (int)std::min<int64_t>(Kf, next - n);
+        if (Kb != pushedK) {
+            decompose(c, hm, rep, c->S_eff, Kb);
+            hipLaunchKernelGGL(k_write_member, dim3(1), dim3(1), 0, s, rep_dev, 0, rep);
+            HIPCHK(c, hipGetLastError());
+            pushedK = Kb;
+        }
+        StepArgs a;
+        a.table = rep_dev;
+        a.first = 0;
+        a.nmembers = 1;
+        a.block_offset = 0;
+        a.total_blocks = rep.blocks;
+        a.parity = cur;
+        a.want_energy = 0;
+        a.want_trace = 0;
+        a.ctx_step = 0;
+        HIPCHK(c, launch_step<T>(a, Kb, hm.face, rep.blocks, s));
+        cur ^= 1;
+        n += Kb;
+        if (n % ck == 0 && n < N) {
+            int rc = store_ckpt(n);
+            if (rc) return rc;
+        }
+    }
+
+    // ---- reverse sweep
+    AdjArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.nx = hm.nx;
+    A.ny = hm.ny;
+    A.ld = hm.ld;
+    A.face = hm.face;
+    A.ax = rep.ax;
+    A.ay = rep.ay;
+    A.h = hm.h;
+    A.hy = hm.hy;
+    A.g1 = G1;
+    A.g2 = g2_out ? G2 : G1;
+    A.R = R;
+    A.trace_grad = tg;
+    // seed lam^N = mu^N = s_N (planes are zero)
+    A.lout = LA[0];
+    A.mout = MU[0];
+    A.rec_col = rec;
+    if (R > 0) HIPCHK(c, launch_adjoint_seed<T>(A, N, s));
+    A.rec_rowptr = rowptr;
+    A.rec_col = rcol;
+    A.rec_id = rid;
+    const void* fu_in = FU[cur];
+    const void* fd_in = FD[cur];
+    int fcur = cur;
+    int lcur = 0;
+    const int Kr = adjoint_K(c);
+    int64_t mtop = N;
+    while (mtop > 0) {
+        if (mtop < N && mtop % ck == 0) {
+            // re-anchor the time reversal on the exact stored state
+            const int64_t k = mtop / ck - 1;
+            fu_in = CU[k];
+            fd_in = CD[k];
+        }
+        const int64_t seg_bot = ((mtop - 1) / ck) * ck;
+        const int Kb = (int)std::min<int64_t>(Kr, mtop - seg_bot);
+        adj_decompose(c, hm, Kb, c->S_eff, A);
+        const int outk = fcur ^ 1;
+        A.uin = fu_in;
+        A.din = fd_in;
+        A.uout = FU[outk];
+        A.dout = FD[outk];
+        A.lin = LA[lcur];
+        A.min = MU[lcur];
+        A.lout = LA[lcur ^ 1];
+        A.mout = MU[lcur ^ 1];
+        A.n_top = mtop;
+        const int grid = (A.waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        HIPCHK(c, launch_adjoint_block<T>(A, Kb, grid, s));
+        fu_in = FU[outk];
+        fd_in = FD[outk];
+        fcur = outk;
+        lcur ^= 1;
+        mtop -= Kb;
+    }
+    HIPCHK(c, launch_grad_out(G1, hm.ld, hm.nx, hm.ny, g1_out, s));
+    if (g2_out) HIPCHK(c, launch_grad_out(G2, hm.ld, hm.nx, hm.ny, g2_out, s));
+    return FDW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fdw_adjoint_workspace_bytes(const fdw_ctx* c, int32_t m, int32_t ckpt_every)
+{
+    if (!c || m < 0 || m >= c->count || ckpt_every < 1) return 0;
+    return adj_layout(c, c->m[m], ckpt_every).total;
+}
+
+int fdw_adjoint(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, const double* trace_grad, int32_t ckpt_every,
+                void* adj_ws, size_t adj_ws_bytes, double* grad_h1, double* grad_h2)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    HostMember& hm = c->m[m];
+    if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
+    if (R < 0 || R > kMaxReceivers) return fail(c, FDW_EINVAL, "R out of range");
+    if (R > 0 && (!recv_ij || !trace_grad)) return fail(c, FDW_EINVAL, "recv_ij and trace_grad are required");
+    if (ckpt_every < 1) return fail(c, FDW_EINVAL, "ckpt_every must be >= 1");
+    if (!adj_ws || ((uintptr_t)adj_ws) % kAlign) return fail(c, FDW_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (!grad_h1) return fail(c, FDW_EINVAL, "grad_h1 is NULL");
+    if (grad_h2 && !hm.face)
+        return fail(c, FDW_EINVAL, "separate dL/dh2 needs a coefficient set with a separate h2");
+    return (c->dtype == FDW_F32)
+               ? adjoint_impl<float>(c, m, recv_ij, R, trace_grad, ckpt_every, adj_ws, adj_ws_bytes, grad_h1, grad_h2)
+               : adjoint_impl<double>(c, m, recv_ij, R, trace_grad, ckpt_every, adj_ws, adj_ws_bytes, grad_h1, grad_h2);
+}
+
+}  // extern "C"
+
+// =============================================================================================
+// Autotuner
+// =============================================================================================
+namespace {
+
+std::string tune_key(const fdw_ctx* c)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    std::ostringstream os;
+    os << arch << " " << (c->dtype == FDW_F32 ? "f32" : "f64") << " " << c->count;
+    for (const HostMember& hm : c->m) os << " " << hm.nx << "x" << hm.ny << (hm.face ? "f" : "n");
+    return os.str();
+}
+
+bool cache_lookup(const std::string& key, int* K, int* S)
+{
+    const char* path = std::getenv("FDW_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const size_t bar = line.rfind('|');
+        if (bar == std::string::npos) continue;
+        if (line.substr(0, bar) != key) continue;
+        std::istringstream is(line.substr(bar + 1));
+        int k = 0, sr = 0;
+        if (is >> k >> sr) {
+            *K = k;
+            *S = sr;
+            found = true;  // last entry wins
+        }
+    }
+    return found;
+}
+
+void cache_store(const std::string& key, int K, int S)
+{
+    const char* path = std::getenv("FDW_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << "|" << K << " " << S << "\n";
+}
+
+}  // namespace
+
+extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
+{
+    if (!c) return FDW_EINVAL;
+    for (const HostMember& hm : c->m) {
+        if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
+        if (hm.n != 0) return fail(c, FDW_ESTATE, "autotune runs from step 0 (call fdw_reset first)");
+    }
+    const std::string key = tune_key(c);
+    int bestK = 0, bestS = 0;
+    if (!cache_lookup(key, &bestK, &bestS)) {
+        int maxny = 0;
+        int64_t points = 0;
+        for (const HostMember& hm : c->m) {
+            maxny = std::max(maxny, hm.ny);
+            points += (int64_t)hm.nx * hm.ny;
+        }
+        int nsteps = steps > 0 ? steps : (int)std::max<int64_t>(16, std::min<int64_t>(256, (int64_t)4e9 / std::max<int64_t>(points, 1)));
+        nsteps = std::max(nsteps, 2 * kMaxTimeBlock);
+        const int Ks32[] = {1, 2, 3, 4, 5, 6, 8};
+        const int Ks64[] = {1, 2, 3, 4};
+        const int* Ks = c->dtype == FDW_F32 ? Ks32 : Ks64;
+        const int nK = c->dtype == FDW_F32 ? 7 : 4;
+        const int Ss[] = {32, 64, 128, 256, 512, 1024};
+        const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode;
+        c->use_graph = 0;
+        c->batch_mode = 0;
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int ki = 0; ki < nK; ++ki) {
+            for (int S : Ss) {
+                if (S > 2 * maxny && S != 32) continue;
+                c->K_cfg = Ks[ki];
+                c->S_cfg = S;
+                c->S_eff = S;
+                int rc = layout_for_K(c, Ks[ki], S);
+                if (rc) return rc;
+                float med = 0.f;
+                std::vector<float> ts;
+                for (int rep = 0; rep < 3; ++rep) {
+                    for (int i = 0; i < c->count; ++i) {
+                        c->m[i].n = 0;
+                        c->m[i].cur = 0;
+                        sync_member_dev(c, i);
+                    }
+                    rc = layout_for_K(c, Ks[ki], S);
+                    if (rc) return rc;
+                    rc = fdw_step_n(c, 1, nullptr);  // start step, outside the timed region
+                    if (rc) return rc;
+                    HIPCHK(c, hipEventRecord(e0, c->stream));
+                    rc = fdw_step_n(c, nsteps, nullptr);
+                    if (rc) return rc;
+                    HIPCHK(c, hipEventRecord(e1, c->stream));
+                    HIPCHK(c, hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                    ts.push_back(ms);
+                }
+                std::sort(ts.begin(), ts.end());
+                med = ts[1];
+                // prefer the smaller time block unless the larger one is at least 2% faster
+                if (med < best * 0.98f || (med < best && Ks[ki] == bestK)) {
+                    best = med;
+                    bestK = Ks[ki];
+                    bestS = S;
+                }
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        c->use_graph = saveG;
+        c->batch_mode = saveB;
+        (void)saveK;
+        (void)saveS;
+        cache_store(key, bestK, bestS);
+    }
+    c->K_cfg = bestK;
+    c->S_cfg = bestS;
+    c->S_eff = bestS;
+    for (int i = 0; i < c->count; ++i) {
+        c->m[i].n = 0;
+        c->m[i].cur = 0;
+        sync_member_dev(c, i);
+    }
+    invalidate_graphs(c);
+    int rc = layout_for_K(c, choose_K(c), c->S_eff);
+    if (rc) return rc;
+    if (best_out) {
+        best_out[0] = bestK;
+        best_out[1] = bestS;
+    }
+    return FDW_OK;
+}

@@ -1,0 +1,130 @@
+// fdw_internal.h - device data layout and kernel launchers of libfdw (gfx950).
+//
+// Layout in HBM: every field of a member is a pitched plane [ny][ld] in the storage type
+// (float or double), x fastest, ld = nx rounded up to a multiple of 64 elements so that
+// every row starts on a 256-byte boundary and a wave's C-element lane vectors are aligned.
+// Columns nx..ld-1 and the boundary ring hold 0 at all times.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdw {
+
+constexpr int kMaxTimeBlock = 8;      // time steps fused in one streaming launch
+constexpr int kWaveSize = 64;         // CDNA wavefront
+constexpr int kWavesPerBlock = 4;     // independent streaming waves per workgroup
+constexpr int kMaxReceivers = 16384;  // per member
+constexpr int kRedBlocks = 1024;      // blocks of the generic two-stage reductions
+
+// Static description of one member, resident in device memory (the member table).
+struct MemberDev {
+    int nx, ny, ld;
+    int face;        // 0: nodal h (h1 == h2) in plane h; 1: face sums FX = h1_i + h1_{i+1} in h, FY in hy
+    int strips;      // streaming work decomposition of the current launch configuration
+    int segs;
+    int seg_rows;
+    int waves;       // strips * segs
+    int blocks;      // ceil(waves / kWavesPerBlock)
+    int block_base;  // first block of this member in an all-member launch
+    int cur0;        // buffer pair holding the state when the launch parity is 0
+    int R;           // receivers (0: no trace recording)
+    int64_t n_offset;    // member step = context step + n_offset
+    int64_t trace_rows;  // N + 1
+    double ax, ay;   // 0.5 tau^2/dx^2, 0.5 tau^2/dy^2 (cast to the storage type in kernels)
+    double escale;   // dx dy / tau^2 (energy)
+    void* u[2];
+    void* d[2];
+    void* h;
+    void* hy;
+    const int* rec_rowptr;  // [ny + 1] CSR of receivers by row
+    const int* rec_col;     // [R] column of each receiver, sorted by (row, column)
+    const int* rec_id;      // [R] position of the receiver in the caller's list
+    void* traces;           // [trace_rows][R]
+    double* epart;          // energy partials [kMaxTimeBlock][max waves]
+    int epart_stride;       // max waves
+    int pad_;
+};
+
+// Per-launch arguments of the streaming stencil.
+struct StepArgs {
+    const MemberDev* table;
+    int nmembers;      // members covered by this launch (table[first .. first+nmembers-1])
+    int first;
+    int block_offset;  // added to blockIdx.x before the member lookup
+    int total_blocks;  // blocks of the launch (for the XCD-aware remap)
+    int parity;        // launch parity: member state pair = cur0 ^ parity
+    int want_energy;
+    int want_trace;
+    int64_t ctx_step;  // context step before this launch
+};
+
+// ---- launchers (fdw_kernels.hip) ---------------------------------------------------------
+// All return hipError_t of the launch.
+template <typename T>
+hipError_t launch_step(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
+template <typename T>
+hipError_t launch_step_persistent(const StepArgs& a, int K, int face_mode, int phases, int grid, int* barrier,
+                                  hipStream_t s);
+template <typename T>
+int persistent_max_blocks(int K, int face_mode);
+
+template <typename T>
+hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
+                                  int64_t energy_stride, int64_t energy_offset, hipStream_t s);
+
+template <typename T>
+hipError_t launch_prepare_coeff(const MemberDev* m_host, const void* h1, const void* h2, int face, double* red,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_start(const MemberDev* m_host, const MemberDev* m_dev, const void* u0, const void* u1, T tau,
+                        int want_energy, int want_trace, double* energy_out, double* red, hipStream_t s);
+template <typename T>
+hipError_t launch_state_energy(const MemberDev* m_host, int cur, double* red, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const void* u, int ld, const int* rec_ij, int R, void* out_row, hipStream_t s);
+template <typename T>
+hipError_t launch_misfit(const void* traces, const double* d, int64_t n, double* J, double* grad, double* red,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_copy_in(const void* src, int nx, int ny, void* dst, int ld, int zero_ring, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_out(const void* src, int ld, int nx, int ny, void* dst, hipStream_t s);
+hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_receivers_csr(const int* rec_ij, int R, int nx, int ny, int* rowptr, int* col, int* id,
+                                int* status, hipStream_t s);
+
+// ---- adjoint (fdw_adjoint.hip) ---------------------------------------------------------
+struct AdjArgs {
+    int nx, ny, ld, face;
+    double ax, ay;
+    const void* h;
+    const void* hy;
+    // state pairs: forward (u, du) and adjoint (lam, mu), in and out
+    const void* uin;
+    const void* din;
+    void* uout;
+    void* dout;
+    const void* lin;
+    const void* min;
+    void* lout;
+    void* mout;
+    double* g1;  // dL/dh1 accumulator (nodal), [ny][ld] double
+    double* g2;  // dL/dh2 accumulator, or equal to g1 when the two are summed
+    const int* rec_rowptr;
+    const int* rec_col;
+    const int* rec_id;
+    int R;
+    const double* trace_grad;  // [N+1][R]
+    int64_t n_top;             // forward step index of the input state u (level n_top)
+    int strips, segs, seg_rows, waves;
+};
+template <typename T>
+hipError_t launch_adjoint_block(const AdjArgs& a, int K, int grid, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint_start_term(const AdjArgs& a, const void* u0, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint_seed(const AdjArgs& a, int64_t N, hipStream_t s);
+hipError_t launch_grad_out(const double* g, int ld, int nx, int ny, double* out, hipStream_t s);
+
+}  // namespace fdw

@@ -1,0 +1,973 @@
+// fdw_kernels.hip - gfx950 kernels of the explicit leapfrog solver of
+//     u_tt = d_x(h1 d_x u) + d_y(h2 d_y u),  zero Dirichlet data,
+// the regularised Cauchy problem of arXiv 2005.11931 (Section 2, eq. (2.1); grid and
+// boundary data of Section 3.3).
+//
+// The hot kernel (k_step) is a y-streaming, temporally blocked sweep.  Each wavefront owns a
+// column strip of the grid and a segment of rows; its 64 lanes hold C consecutive columns
+// each (one 16-byte vector per lane and row, so a wave reads 1 KiB contiguous per row and
+// array).  The wave walks down its segment one row at a time and advances K time levels at
+// once: level t computes row j - t from level t-1's rows j-t-1 .. j-t+1, which it holds in
+// registers, so every input element is read from HBM once per K steps and every output is
+// written once per K steps.  Horizontal neighbours cross lanes with DPP wave shifts; the
+// strip carries a K-column halo on each side (recomputed, never written) so that waves are
+// independent and need no barrier.  All variants (any K, any segment length, batched or
+// not) evaluate each grid point with the same function in the same operation order, so
+// their results agree bit for bit.
+//
+// State: increment form (u^n, du^n = u^n - u^{n-1}); the step is
+//     du^{n+1} = du^n + L(u^n),   u^{n+1} = u^n + du^{n+1},   L = tau^2 A(h),
+// identical to u^{n+1} = 2u^n - u^{n-1} + tau^2 A u^n in exact arithmetic.
+// Energy (discrete CL-01 of Section 2): E^{n+1/2} = (dx dy / tau^2) sum (du^{n+1})^2 - u^{n+1} L(u^n),
+// accumulated in FP64 per wave, reduced in a fixed order.
+#include "fdw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace fdw {
+
+// ------------------------------------------------------------------------------------------
+// Lane exchange across the whole wave (DPP wave shift by one lane; lanes with no source get 0)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int lane_from_left_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // lane l <- lane l-1
+}
+__device__ __forceinline__ int lane_from_right_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // lane l <- lane l+1
+}
+__device__ __forceinline__ float lane_from_left(float v)
+{
+    return __builtin_bit_cast(float, lane_from_left_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float lane_from_right(float v)
+{
+    return __builtin_bit_cast(float, lane_from_right_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_from_left(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = lane_from_left_i((int)(b & 0xffffffffLL));
+    int hi = lane_from_left_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_right(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = lane_from_right_i((int)(b & 0xffffffffLL));
+    int hi = lane_from_right_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ------------------------------------------------------------------------------------------
+// The point update, shared by every kernel that advances the state.
+//   f* are face sums (2x the face coefficient: h_c + h_neighbour), ax = tau^2/(2 dx^2).
+// Opposite faces are added as commutative pairs so that mirror-symmetric data stay
+// mirror-symmetric bit for bit.  The file is compiled without contraction; the one fused
+// multiply-add is explicit.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T flux_L(T uc, T ue, T uw, T un, T us, T fxe, T fxw, T fyn, T fys, T ax, T ay)
+{
+    T pe = fxe * (ue - uc);
+    T pw = fxw * (uw - uc);
+    T pn = fyn * (un - uc);
+    T ps = fys * (us - uc);
+    T sx = pe + pw;
+    T sy = pn + ps;
+    return __builtin_fma(ax, sx, ay * sy);
+}
+template <>
+__device__ __forceinline__ float flux_L<float>(float uc, float ue, float uw, float un, float us, float fxe, float fxw,
+                                               float fyn, float fys, float ax, float ay)
+{
+    float pe = fxe * (ue - uc);
+    float pw = fxw * (uw - uc);
+    float pn = fyn * (un - uc);
+    float ps = fys * (us - uc);
+    float sx = pe + pw;
+    float sy = pn + ps;
+    return __builtin_fmaf(ax, sx, ay * sy);
+}
+
+template <typename T, int C>
+struct alignas(sizeof(T) * C) Pack {
+    T v[C];
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void load_pack(const T* __restrict__ p, T (&out)[C])
+{
+    Pack<T, C> q = *reinterpret_cast<const Pack<T, C>*>(p);
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = q.v[c];
+}
+template <typename T, int C>
+__device__ __forceinline__ void store_pack(T* __restrict__ p, const T (&in)[C])
+{
+    Pack<T, C> q;
+#pragma unroll
+    for (int c = 0; c < C; ++c) q.v[c] = in[c];
+    *reinterpret_cast<Pack<T, C>*>(p) = q;
+}
+
+template <typename T>
+struct Lanes;  // columns per lane: one 16-byte vector
+template <>
+struct Lanes<float> {
+    static constexpr int C = 4;
+};
+template <>
+struct Lanes<double> {
+    static constexpr int C = 2;
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give each
+    // XCD a contiguous range of logical blocks so that neighbouring strips share an L2.
+    int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+    return xcd * per + min(xcd, rem) + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// One streaming work item: member M, strip, segment; K time levels.
+// ------------------------------------------------------------------------------------------
+template <typename T, int K, int FACE>
+__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step, int want_energy,
+                                           int want_trace)
+{
+    constexpr int C = Lanes<T>::C;
+    constexpr int Hx = ((K + C - 1) / C) * C;  // halo columns on each side (multiple of C)
+    constexpr int Wv = kWaveSize * C - 2 * Hx;  // owned columns per strip
+    const int lane = threadIdx.x & 63;
+
+    const int nx = M.nx, ny = M.ny, ld = M.ld;
+    const int strip = wave % M.strips;
+    const int seg = wave / M.strips;
+    const int ws = strip * Wv - Hx;
+    const int cb = ws + lane * C;
+    const bool lane_live = (cb >= 0) && (cb < ld);
+    const bool lane_owned = lane_live && (lane * C >= Hx) && (lane * C < Hx + Wv);
+    bool colin[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) colin[c] = (cb + c >= 1) && (cb + c <= nx - 2);
+
+    const int r0 = seg * M.seg_rows;
+    const int r1 = min(r0 + M.seg_rows, ny);
+    const int cur = M.cur0 ^ parity;
+    const T* __restrict__ uin = (const T*)M.u[cur];
+    const T* __restrict__ din = (const T*)M.d[cur];
+    T* __restrict__ uout = (T*)M.u[cur ^ 1];
+    T* __restrict__ dout = (T*)M.d[cur ^ 1];
+    const T* __restrict__ hp = (const T*)M.h;
+    const T* __restrict__ hyp = (const T*)M.hy;
+    const T ax = (T)M.ax, ay = (T)M.ay;
+    const int64_t n0 = ctx_step + M.n_offset;
+
+    // Level rings: U[t] holds level t at rows (r-1, r, r+1) for the row r that level t+1
+    // computes next; D[t] holds level t's increment at rows (r, r+1).
+    T U[K][3][C];
+    T D[K][2][C];
+    // Coefficient rings.  Nodal: rows j-K-1 .. j with one halo column per side.
+    // Face: FX rows j-K .. j with the left halo column, FY rows j-K-1 .. j.
+    constexpr int HR = FACE ? 1 : (K + 2);
+    constexpr int XR = FACE ? (K + 1) : 1;
+    constexpr int YR = FACE ? (K + 2) : 1;
+    T Hn[HR][C + 2];
+    T FX[XR][C + 1];
+    T FY[YR][C];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            U[t][0][c] = U[t][1][c] = U[t][2][c] = T(0);
+            D[t][0][c] = D[t][1][c] = T(0);
+        }
+#pragma unroll
+    for (int q = 0; q < HR; ++q)
+#pragma unroll
+        for (int c = 0; c < C + 2; ++c) Hn[q][c] = T(0);
+#pragma unroll
+    for (int q = 0; q < XR; ++q)
+#pragma unroll
+        for (int c = 0; c < C + 1; ++c) FX[q][c] = T(0);
+#pragma unroll
+    for (int q = 0; q < YR; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c) FY[q][c] = T(0);
+
+    double acc[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) acc[t] = 0.0;
+
+    for (int j = r0 - K; j < r1 + K; ++j) {
+        // ---- level 0: row j of the input state and of the coefficient
+        T nu0[C], nd0[C], nh0[C], ny0[C];
+        const bool rl = lane_live && (j >= 0) && (j < ny);
+        if (rl) {
+            const size_t off = (size_t)j * ld + cb;
+            load_pack<T, C>(uin + off, nu0);
+            load_pack<T, C>(din + off, nd0);
+            load_pack<T, C>(hp + off, nh0);
+            if (FACE) load_pack<T, C>(hyp + off, ny0);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) nu0[c] = nd0[c] = nh0[c] = ny0[c] = T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            U[0][0][c] = U[0][1][c];
+            U[0][1][c] = U[0][2][c];
+            U[0][2][c] = nu0[c];
+            D[0][0][c] = D[0][1][c];
+            D[0][1][c] = nd0[c];
+        }
+        if (FACE) {
+#pragma unroll
+            for (int q = 0; q < XR - 1; ++q)
+#pragma unroll
+                for (int c = 0; c < C + 1; ++c) FX[q][c] = FX[q + 1][c];
+            FX[XR - 1][0] = lane_from_left(nh0[C - 1]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) FX[XR - 1][c + 1] = nh0[c];
+#pragma unroll
+            for (int q = 0; q < YR - 1; ++q)
+#pragma unroll
+                for (int c = 0; c < C; ++c) FY[q][c] = FY[q + 1][c];
+#pragma unroll
+            for (int c = 0; c < C; ++c) FY[YR - 1][c] = ny0[c];
+        } else {
+#pragma unroll
+            for (int q = 0; q < HR - 1; ++q)
+#pragma unroll
+                for (int c = 0; c < C + 2; ++c) Hn[q][c] = Hn[q + 1][c];
+            Hn[HR - 1][0] = lane_from_left(nh0[C - 1]);
+            Hn[HR - 1][C + 1] = lane_from_right(nh0[0]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) Hn[HR - 1][c + 1] = nh0[c];
+        }
+
+        // ---- levels 1..K: level t computes row r = j - t
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            const int r = j - t;
+            const bool rin = (r >= 1) && (r <= ny - 2);
+            const bool rown = (r >= r0) && (r < r1);
+            const T left = lane_from_left(U[t - 1][1][C - 1]);
+            const T right = lane_from_right(U[t - 1][1][0]);
+            T nu[C], nd[C], L[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T uc = U[t - 1][1][c];
+                const T ue = (c < C - 1) ? U[t - 1][1][c + 1] : right;
+                const T uw = (c > 0) ? U[t - 1][1][c - 1] : left;
+                const T un = U[t - 1][2][c];
+                const T us = U[t - 1][0][c];
+                T fxe, fxw, fyn, fys;
+                if (FACE) {
+                    fxe = FX[K - t][c + 1];
+                    fxw = FX[K - t][c];
+                    fyn = FY[K + 1 - t][c];
+                    fys = FY[K - t][c];
+                } else {
+                    const int q = K + 1 - t;
+                    const T hc = Hn[q][c + 1];
+                    fxe = hc + Hn[q][c + 2];
+                    fxw = Hn[q][c] + hc;
+                    fyn = hc + Hn[q + 1][c + 1];
+                    fys = Hn[q - 1][c + 1] + hc;
+                }
+                L[c] = flux_L<T>(uc, ue, uw, un, us, fxe, fxw, fyn, fys, ax, ay);
+                const bool in = rin && colin[c];
+                nd[c] = in ? (D[t - 1][0][c] + L[c]) : T(0);
+                nu[c] = in ? (uc + nd[c]) : T(0);
+            }
+            if (want_energy && rown && lane_owned) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const double dd = (double)nd[c], uu = (double)nu[c], ll = (double)L[c];
+                    acc[t - 1] += __builtin_fma(-uu, ll, dd * dd);
+                }
+            }
+            if (want_trace && rown && rin) {
+                const int kb = M.rec_rowptr[r], ke = M.rec_rowptr[r + 1];
+                const int64_t row = n0 + t;
+                if (kb < ke && row < M.trace_rows) {
+                    for (int k = kb; k < ke; ++k) {
+                        const int col = M.rec_col[k];
+                        const int off = col - cb;
+                        if (lane_owned && off >= 0 && off < C) {
+                            T v = nu[0];
+#pragma unroll
+                            for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
+                            ((T*)M.traces)[row * M.R + M.rec_id[k]] = v;
+                        }
+                    }
+                }
+            }
+            if (t < K) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    U[t][0][c] = U[t][1][c];
+                    U[t][1][c] = U[t][2][c];
+                    U[t][2][c] = nu[c];
+                    D[t][0][c] = D[t][1][c];
+                    D[t][1][c] = nd[c];
+                }
+            } else if (rown && lane_owned) {
+                const size_t off = (size_t)r * ld + cb;
+                store_pack<T, C>(uout + off, nu);
+                store_pack<T, C>(dout + off, nd);
+            }
+        }
+    }
+
+    if (want_energy) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const double s = wave_sum(acc[t]);
+            if (lane == 0) M.epart[(size_t)t * M.epart_stride + wave] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ int find_member(const MemberDev* table, int first, int nmembers, int gb)
+{
+    int m = first;
+    for (int k = first + 1; k < first + nmembers; ++k)
+        if (table[k].block_base <= gb) m = k;
+    return m;
+}
+
+template <typename T, int K, int FACE>
+__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step(StepArgs a)
+{
+    const int gb = xcd_remap(blockIdx.x, a.total_blocks) + a.block_offset;
+    const int m = find_member(a.table, a.first, a.nmembers, gb);
+    const MemberDev& M = a.table[m];
+    const int wave = (gb - M.block_base) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wave >= M.waves) return;
+    sweep_item<T, K, FACE>(M, wave, a.parity, a.ctx_step, a.want_energy, a.want_trace);
+}
+
+template <typename T, int K>
+static hipError_t launch_step_k(const StepArgs& a, int face_mode, int grid, hipStream_t s)
+{
+    if (face_mode == 1)
+        hipLaunchKernelGGL((k_step<T, K, 1>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step<T, K, 0>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_step_k<T, 1>(a, face_mode, grid, s);
+    case 2: return launch_step_k<T, 2>(a, face_mode, grid, s);
+    case 3: return launch_step_k<T, 3>(a, face_mode, grid, s);
+    case 4: return launch_step_k<T, 4>(a, face_mode, grid, s);
+    case 5: return launch_step_k<T, 5>(a, face_mode, grid, s);
+    case 6: return launch_step_k<T, 6>(a, face_mode, grid, s);
+    case 7: return launch_step_k<T, 7>(a, face_mode, grid, s);
+    case 8: return launch_step_k<T, 8>(a, face_mode, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_step<float>(const StepArgs&, int, int, int, hipStream_t);
+template hipError_t launch_step<double>(const StepArgs&, int, int, int, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Persistent batched variant: one cooperative launch runs `phases` time blocks of K steps
+// (plus a final block of tail_K steps) over all members, with a grid-wide barrier between
+// time blocks.  The barrier spin is bounded: on expiry it records an error flag and lets the
+// wave continue, so a launch always drains.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
+{
+    // every wave publishes its own stores before the block arrives ...
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1L << 26)) {
+                    __hip_atomic_fetch_or(&bar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+    }
+    gen += 1;
+    __syncthreads();
+    // ... and every wave sees the other blocks' stores afterwards
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T, int K, int FACE>
+__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar)
+{
+    const int total_waves = a.total_blocks * kWavesPerBlock;  // work items of one time block
+    const int gw0 = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int stride = gridDim.x * kWavesPerBlock;
+    int gen = 0;
+    int parity = a.parity;
+    int64_t step = a.ctx_step;
+    for (int p = 0; p < phases; ++p) {
+        for (int item = gw0; item < total_waves; item += stride) {
+            const int gb = item / kWavesPerBlock + a.block_offset;
+            const int m = find_member(a.table, a.first, a.nmembers, gb);
+            const MemberDev& M = a.table[m];
+            const int wave = (gb - M.block_base) * kWavesPerBlock + (item % kWavesPerBlock);
+            if (wave < M.waves) sweep_item<T, K, FACE>(M, wave, parity, step, 0, 0);
+        }
+        parity ^= 1;
+        step += K;
+        if (p + 1 < phases) grid_barrier(bar, gridDim.x, gen);
+    }
+}
+
+template <typename T, int K>
+static hipError_t launch_persistent_k(const StepArgs& a, int face_mode, int phases, int grid, int* bar, hipStream_t s)
+{
+    void* args[] = {(void*)&a, (void*)&phases, (void*)&bar};
+    if (face_mode == 1)
+        return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, 1>, dim3(grid),
+                                          dim3(kWaveSize * kWavesPerBlock), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, 0>, dim3(grid),
+                                      dim3(kWaveSize * kWavesPerBlock), args, 0, s);
+}
+
+template <typename T>
+hipError_t launch_step_persistent(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                  hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_persistent_k<T, 1>(a, face_mode, phases, grid, bar, s);
+    case 2: return launch_persistent_k<T, 2>(a, face_mode, phases, grid, bar, s);
+    case 4: return launch_persistent_k<T, 4>(a, face_mode, phases, grid, bar, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_step_persistent<float>(const StepArgs&, int, int, int, int, int*, hipStream_t);
+template hipError_t launch_step_persistent<double>(const StepArgs&, int, int, int, int, int*, hipStream_t);
+
+template <typename T>
+int persistent_max_blocks(int K, int face_mode)
+{
+    int per_cu = 0;
+    hipError_t e;
+    const int bs = kWaveSize * kWavesPerBlock;
+    if (K == 1)
+        e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 1, 1>, bs, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 1, 0>, bs, 0);
+    else if (K == 2)
+        e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 2, 1>, bs, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 2, 0>, bs, 0);
+    else
+        e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 4, 1>, bs, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 4, 0>, bs, 0);
+    if (e != hipSuccess) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+template int persistent_max_blocks<float>(int, int);
+template int persistent_max_blocks<double>(int, int);
+
+// ------------------------------------------------------------------------------------------
+// Energy finalisation: E = escale * sum over waves of the per-wave partials, fixed order.
+// grid = (levels, nmembers)
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table, int first, double* energy_base,
+                                                         int64_t energy_stride, int64_t energy_offset)
+{
+    const int t = blockIdx.x;
+    const int m = first + blockIdx.y;
+    const MemberDev& M = table[m];
+    const double* p = M.epart + (size_t)t * M.epart_stride;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < M.waves; w += 256) s += p[w];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) energy_base[(int64_t)m * energy_stride + energy_offset + t] = red[0] * M.escale;
+}
+
+template <typename T>
+hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
+                                  int64_t energy_stride, int64_t energy_offset, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_finalize, dim3(levels, nmembers), dim3(256), 0, s, table, first, energy_base,
+                       energy_stride, energy_offset);
+    return hipGetLastError();
+}
+template hipError_t launch_energy_finalize<float>(const MemberDev*, int, int, int, double*, int64_t, int64_t,
+                                                  hipStream_t);
+template hipError_t launch_energy_finalize<double>(const MemberDev*, int, int, int, double*, int64_t, int64_t,
+                                                   hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Block reduction helpers (fixed order) for the generic two-stage reductions.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Sum of partials[0..n) into *out, fixed order (one block of 256).
+__global__ __launch_bounds__(256) void k_sum_partials(const double* partials, int n, double scale, double* out)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s * scale;
+}
+
+// ------------------------------------------------------------------------------------------
+// a1: coefficient preparation.  Nodal layout: copy h (dense) into the pitched plane.  Face
+// layout: FX = h1_i + h1_{i+1}, FY = h2_j + h2_{j+1} (twice the face means).  Statistics for
+// validation and the stability check go to red[]: per block {min h, max hx face, max hy face,
+// non-finite count}.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_prepare_coeff(const T* __restrict__ h1, const T* __restrict__ h2, int nx,
+                                                       int ny, int ld, int face, T* __restrict__ H, T* __restrict__ HY,
+                                                       double* red)
+{
+    __shared__ double sh[256];
+    double mn = 1e300, mx = 0.0, my = 0.0, bad = 0.0;
+    const int64_t total = (int64_t)ld * ny;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+        const int j = (int)(k / ld), i = (int)(k % ld);
+        if (i >= nx) {
+            H[k] = T(0);
+            if (face) HY[k] = T(0);
+            continue;
+        }
+        const T a = h1[(size_t)j * nx + i];
+        const T b = h2[(size_t)j * nx + i];
+        const double ad = (double)a, bd = (double)b;
+        if (!(ad == ad) || ad - ad != 0.0 || !(bd == bd) || bd - bd != 0.0) bad += 1.0;
+        mn = fmin(mn, fmin(ad, bd));
+        if (i < nx - 1) mx = fmax(mx, 0.5 * (ad + (double)h1[(size_t)j * nx + i + 1]));
+        if (j < ny - 1) my = fmax(my, 0.5 * (bd + (double)h2[(size_t)(j + 1) * nx + i]));
+        if (face) {
+            H[k] = (i < nx - 1) ? (a + h1[(size_t)j * nx + i + 1]) : T(0);
+            HY[k] = (j < ny - 1) ? (b + h2[(size_t)(j + 1) * nx + i]) : T(0);
+        } else {
+            H[k] = a;
+        }
+    }
+    // block min/max via shared memory (order-independent)
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x * 4 + 0] = sh[0];
+    __syncthreads();
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x * 4 + 1] = sh[0];
+    __syncthreads();
+    sh[threadIdx.x] = my;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x * 4 + 2] = sh[0];
+    __syncthreads();
+    const double nb = block_sum(bad, sh);
+    if (threadIdx.x == 0) red[blockIdx.x * 4 + 3] = nb;
+}
+
+__global__ __launch_bounds__(256) void k_coeff_stats_final(double* red, int nblocks)
+{
+    __shared__ double sh[256];
+    double mn = 1e300, mx = 0.0, my = 0.0, bad = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        mn = fmin(mn, red[b * 4 + 0]);
+        mx = fmax(mx, red[b * 4 + 1]);
+        my = fmax(my, red[b * 4 + 2]);
+        bad += red[b * 4 + 3];
+    }
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double rmn = sh[0];
+    __syncthreads();
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double rmx = sh[0];
+    __syncthreads();
+    sh[threadIdx.x] = my;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double rmy = sh[0];
+    __syncthreads();
+    const double rb = block_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        // results land after the per-block area: red[4*kRedBlocks + 0..3]
+        red[4 * kRedBlocks + 0] = rmn;
+        red[4 * kRedBlocks + 1] = rmx;
+        red[4 * kRedBlocks + 2] = rmy;
+        red[4 * kRedBlocks + 3] = rb;
+    }
+}
+
+template <typename T>
+hipError_t launch_prepare_coeff(const MemberDev* m, const void* h1, const void* h2, int face, double* red,
+                                hipStream_t s)
+{
+    const int64_t total = (int64_t)m->ld * m->ny;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > kRedBlocks) blocks = kRedBlocks;
+    hipLaunchKernelGGL((k_prepare_coeff<T>), dim3(blocks), dim3(256), 0, s, (const T*)h1, (const T*)(h2 ? h2 : h1),
+                       m->nx, m->ny, m->ld, face, (T*)m->h, (T*)m->hy, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_coeff_stats_final, dim3(1), dim3(256), 0, s, red, blocks);
+    return hipGetLastError();
+}
+template hipError_t launch_prepare_coeff<float>(const MemberDev*, const void*, const void*, int, double*, hipStream_t);
+template hipError_t launch_prepare_coeff<double>(const MemberDev*, const void*, const void*, int, double*, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// a2: start step.  du^1 = tau u1 + L(u^0)/2, u^1 = u^0 + du^1 (interior), written to pair 0;
+// energy partials per block into red[], optional trace row 1.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void face_sums(const MemberDev& M, const T* hp, const T* hyp, int j, int i, T& fxe, T& fxw,
+                                          T& fyn, T& fys)
+{
+    const size_t k = (size_t)j * M.ld + i;
+    if (M.face) {
+        fxe = hp[k];
+        fxw = hp[k - 1];
+        fyn = hyp[k];
+        fys = hyp[k - M.ld];
+    } else {
+        const T hc = hp[k];
+        fxe = hc + hp[k + 1];
+        fxw = hp[k - 1] + hc;
+        fyn = hc + hp[k + M.ld];
+        fys = hp[k - M.ld] + hc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_start(MemberDev M, const T* __restrict__ u0, const T* __restrict__ u1, T tau,
+                                               int want_energy, double* red)
+{
+    __shared__ double sh[256];
+    const T* hp = (const T*)M.h;
+    const T* hyp = (const T*)M.hy;
+    T* uo = (T*)M.u[0];
+    T* dout = (T*)M.d[0];
+    const T ax = (T)M.ax, ay = (T)M.ay;
+    double acc = 0.0;
+    const int64_t total = (int64_t)M.ld * M.ny;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+        const int j = (int)(k / M.ld), i = (int)(k % M.ld);
+        const bool in = (i >= 1) && (i <= M.nx - 2) && (j >= 1) && (j <= M.ny - 2);
+        T nu = T(0), nd = T(0);
+        if (in) {
+            T fxe, fxw, fyn, fys;
+            face_sums<T>(M, hp, hyp, j, i, fxe, fxw, fyn, fys);
+            const T uc = u0[k];
+            const T L = flux_L<T>(uc, u0[k + 1], u0[k - 1], u0[k + M.ld], u0[k - M.ld], fxe, fxw, fyn, fys, ax, ay);
+            const T a = tau * u1[k];
+            const T b = T(0.5) * L;
+            nd = a + b;
+            nu = uc + nd;
+            if (want_energy) acc += __builtin_fma(-(double)nu, (double)L, (double)nd * (double)nd);
+        }
+        uo[k] = nu;
+        dout[k] = nd;
+    }
+    if (want_energy) {
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) red[blockIdx.x] = s;
+    }
+}
+
+template <typename T>
+hipError_t launch_start(const MemberDev* m, const MemberDev* m_dev, const void* u0, const void* u1, T tau,
+                        int want_energy, int want_trace, double* energy_out, double* red, hipStream_t s)
+{
+    const int64_t total = (int64_t)m->ld * m->ny;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > kRedBlocks) blocks = kRedBlocks;
+    hipLaunchKernelGGL((k_start<T>), dim3(blocks), dim3(256), 0, s, *m, (const T*)u0, (const T*)u1, tau, want_energy,
+                       red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (want_energy) {
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, red, blocks, m->escale, energy_out);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    (void)m_dev;
+    (void)want_trace;
+    return hipSuccess;
+}
+template hipError_t launch_start<float>(const MemberDev*, const MemberDev*, const void*, const void*, float, int, int,
+                                        double*, double*, hipStream_t);
+template hipError_t launch_start<double>(const MemberDev*, const MemberDev*, const void*, const void*, double, int,
+                                         int, double*, double*, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// E^{n-1/2} of a stored state (u^n, du^n): escale * sum du^2 - (u - du) L(u).
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_state_energy(MemberDev M, int cur, double* red)
+{
+    __shared__ double sh[256];
+    const T* hp = (const T*)M.h;
+    const T* hyp = (const T*)M.hy;
+    const T* u = (const T*)M.u[cur];
+    const T* du = (const T*)M.d[cur];
+    const T ax = (T)M.ax, ay = (T)M.ay;
+    double acc = 0.0;
+    const int64_t total = (int64_t)M.ld * M.ny;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+        const int j = (int)(k / M.ld), i = (int)(k % M.ld);
+        if (i < 1 || i > M.nx - 2 || j < 1 || j > M.ny - 2) continue;
+        T fxe, fxw, fyn, fys;
+        face_sums<T>(M, hp, hyp, j, i, fxe, fxw, fyn, fys);
+        const T L = flux_L<T>(u[k], u[k + 1], u[k - 1], u[k + M.ld], u[k - M.ld], fxe, fxw, fyn, fys, ax, ay);
+        const double d = (double)du[k];
+        const double prev = (double)u[k] - d;
+        acc += __builtin_fma(-prev, (double)L, d * d);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+template <typename T>
+hipError_t launch_state_energy(const MemberDev* m, int cur, double* red, double* out, hipStream_t s)
+{
+    const int64_t total = (int64_t)m->ld * m->ny;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > kRedBlocks) blocks = kRedBlocks;
+    hipLaunchKernelGGL((k_state_energy<T>), dim3(blocks), dim3(256), 0, s, *m, cur, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, red, blocks, m->escale, out);
+    return hipGetLastError();
+}
+template hipError_t launch_state_energy<float>(const MemberDev*, int, double*, double*, hipStream_t);
+template hipError_t launch_state_energy<double>(const MemberDev*, int, double*, double*, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// a7: trace gather of one state row, and the FP64 misfit with its adjoint source.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_gather(const T* __restrict__ u, int ld, const int* __restrict__ rec_ij, int R, T* __restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) out[r] = u[(size_t)rec_ij[2 * r + 1] * ld + rec_ij[2 * r]];
+}
+template <typename T>
+hipError_t launch_gather(const void* u, int ld, const int* rec_ij, int R, void* out_row, hipStream_t s)
+{
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather<T>), dim3((R + 255) / 256), dim3(256), 0, s, (const T*)u, ld, rec_ij, R, (T*)out_row);
+    return hipGetLastError();
+}
+template hipError_t launch_gather<float>(const void*, int, const int*, int, void*, hipStream_t);
+template hipError_t launch_gather<double>(const void*, int, const int*, int, void*, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_misfit(const T* __restrict__ tr, const double* __restrict__ d, int64_t n,
+                                                double* __restrict__ grad, double* red)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        const double e = (double)tr[k] - d[k];
+        acc += e * e;
+        if (grad) grad[k] = 2.0 * e;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+template <typename T>
+hipError_t launch_misfit(const void* traces, const double* d, int64_t n, double* J, double* grad, double* red,
+                         hipStream_t s)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > kRedBlocks) blocks = kRedBlocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_misfit<T>), dim3(blocks), dim3(256), 0, s, (const T*)traces, d, n, grad, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, red, blocks, 1.0, J);
+    return hipGetLastError();
+}
+template hipError_t launch_misfit<float>(const void*, const double*, int64_t, double*, double*, double*, hipStream_t);
+template hipError_t launch_misfit<double>(const void*, const double*, int64_t, double*, double*, double*, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Layout conversion: dense caller arrays <-> pitched planes (boundary ring zeroed on input).
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_copy_in(const T* __restrict__ src, int nx, int ny, T* __restrict__ dst, int ld, int zero_ring)
+{
+    const int64_t total = (int64_t)ld * ny;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(k / ld), i = (int)(k % ld);
+        T v = T(0);
+        if (i < nx) {
+            const bool ring = (i == 0) || (j == 0) || (i == nx - 1) || (j == ny - 1);
+            v = (zero_ring && ring) ? T(0) : src[(size_t)j * nx + i];
+        }
+        dst[k] = v;
+    }
+}
+template <typename T>
+hipError_t launch_copy_in(const void* src, int nx, int ny, void* dst, int ld, int zero_ring, hipStream_t s)
+{
+    const int64_t total = (int64_t)ld * ny;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((k_copy_in<T>), dim3(blocks), dim3(256), 0, s, (const T*)src, nx, ny, (T*)dst, ld, zero_ring);
+    return hipGetLastError();
+}
+template hipError_t launch_copy_in<float>(const void*, int, int, void*, int, int, hipStream_t);
+template hipError_t launch_copy_in<double>(const void*, int, int, void*, int, int, hipStream_t);
+
+template <typename T>
+__global__ void k_copy_out(const T* __restrict__ src, int ld, int nx, int ny, T* __restrict__ dst)
+{
+    const int64_t total = (int64_t)nx * ny;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(k / nx), i = (int)(k % nx);
+        dst[k] = src[(size_t)j * ld + i];
+    }
+}
+template <typename T>
+hipError_t launch_copy_out(const void* src, int ld, int nx, int ny, void* dst, hipStream_t s)
+{
+    const int64_t total = (int64_t)nx * ny;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((k_copy_out<T>), dim3(blocks), dim3(256), 0, s, (const T*)src, ld, nx, ny, (T*)dst);
+    return hipGetLastError();
+}
+template hipError_t launch_copy_out<float>(const void*, int, int, int, void*, hipStream_t);
+template hipError_t launch_copy_out<double>(const void*, int, int, int, void*, hipStream_t);
+
+__global__ void k_fill_bytes(uint4* p, size_t n16, unsigned char* tail, size_t ntail)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+        p[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    // p is 256-byte aligned (workspace carving); bytes may have a tail below 16
+    const size_t n16 = bytes / 16;
+    const size_t ntail = bytes - n16 * 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_bytes, dim3((unsigned)blocks), dim3(256), 0, s, (uint4*)p, n16,
+                       (unsigned char*)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+// Receivers (i, j) -> CSR by row, sorted by (row, column), with validation.  One block; R is
+// at most kMaxReceivers.  status[0] = 0 on success, 1 if a receiver is not an interior node.
+__global__ __launch_bounds__(256) void k_receivers_csr(const int* __restrict__ rec, int R, int nx, int ny,
+                                                       int* __restrict__ rowptr, int* __restrict__ col,
+                                                       int* __restrict__ id, int* status)
+{
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += 256) {
+        const int i = rec[2 * r], j = rec[2 * r + 1];
+        if (i < 1 || i > nx - 2 || j < 1 || j > ny - 2) atomicOr(&bad, 1);
+    }
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) status[0] = 1;
+        return;
+    }
+    // rank of each receiver in (row, column, index) order: O(R^2 / 256), fine for R <= 16384
+    for (int r = threadIdx.x; r < R; r += 256) {
+        const int i = rec[2 * r], j = rec[2 * r + 1];
+        int rank = 0;
+        for (int q = 0; q < R; ++q) {
+            const int iq = rec[2 * q], jq = rec[2 * q + 1];
+            const bool before = (jq < j) || (jq == j && (iq < i || (iq == i && q < r)));
+            rank += before ? 1 : 0;
+        }
+        col[rank] = i;
+        id[rank] = r;
+    }
+    // row pointers: rowptr[y] = number of receivers with row < y
+    for (int y = threadIdx.x; y <= ny; y += 256) {
+        int c = 0;
+        for (int q = 0; q < R; ++q) c += (rec[2 * q + 1] < y) ? 1 : 0;
+        rowptr[y] = c;
+    }
+    if (threadIdx.x == 0) status[0] = 0;
+}
+hipError_t launch_receivers_csr(const int* rec_ij, int R, int nx, int ny, int* rowptr, int* col, int* id, int* status,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_receivers_csr, dim3(1), dim3(256), 0, s, rec_ij, R, nx, ny, rowptr, col, id, status);
+    return hipGetLastError();
+}
+
+}  // namespace fdw
