@@ -1,0 +1,292 @@
+"""Benchmark of the explicit leapfrog wave solver on one MI355X.
+
+One bench step = the whole forward hot path over the 8192 x 8192 point-singularity workload
+(h = 1 + 5 phi_eps(r), eps = 4 dx, four seeded humps, tau = 0.5 dx / sqrt(max h)):
+face/validation of the coefficient, Taylor start, 5000 leapfrog steps with the discrete
+energy of every step, and a snapshot of the final field.  Inputs are resident in HBM before
+the timed region.  `value` = interior grid-point updates per second (FP32 storage).
+
+Also reported (same JSON line): the same workload in FP64, the 32-member batched family of
+regularisations (512^2 .. 4096^2, 2000 steps each, one persistent launch), the adjoint /
+forward time ratio of the 2048^2 FP64 receiver-misfit gradient (4000 steps, checkpoints every
+64), the roofline of the dominant kernel (HIP events on the solver's stream) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "grid-point updates/s + % HBM roofline (fwd, batched); adjoint/forward time ratio"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fdw_kernels.hip", "fdw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2005_11931_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name: str, launch_nodes: int):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def forward_bench(fdw, torch, I, dtype, steps, warmup, n=8192, nsteps=5000):
+    case = I.point_case(n=n, nsteps=nsteps)
+    td = fdw.torch_dtype(dtype)
+    s = fdw.solver_for_case(case, dtype=dtype)
+    h = torch.as_tensor(case.h1, dtype=td, device="cuda")
+    energy = torch.empty((1, nsteps), dtype=torch.float64, device="cuda")
+    snap = torch.empty((n, n), dtype=td, device="cuda")
+    del case
+    updates = (n - 2) * (n - 2) * nsteps
+
+    def one():
+        s.set_coeff(h)
+        s.step_into(nsteps, energy)
+        s._check(fdw.lib().fdw_get_state(s.ctx, 0, fdw._ptr(snap), None, None))
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    e = energy[0].cpu().numpy()
+    drift = float(abs(e - e[0]).max() / e[0])
+    # dominant kernel: the streaming stencil; average launch duration from HIP events
+    s.configure(fdw.FDW_CFG_TIMING, 1)
+    s.kernel_time()
+    s.set_coeff(h)
+    s.step_into(nsteps, energy)
+    ms, launches = s.kernel_time()
+    K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    S = s.config(fdw.FDW_CFG_SEGMENT_ROWS)
+    s.configure(fdw.FDW_CFG_TIMING, 0)
+    s.close()
+    return dict(sec=dt, updates=updates, ups=updates / dt, drift=drift, kernel_ms=ms, launches=launches, K=K, S=S,
+                n=n, nsteps=nsteps)
+
+
+def family_bench(fdw, torch, I, steps, warmup):
+    fam = I.family()
+    s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
+    s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+    nsteps = fam[0].nsteps
+    updates = sum((c.nx - 2) * (c.ny - 2) * c.nsteps for c in fam)
+    bytes_alg = sum(c.nx * c.ny for c in fam) * 5 * 4 * nsteps / s.config(fdw.FDW_CFG_TIME_BLOCK)
+    del fam
+
+    def one():
+        for m in range(s.count):
+            s.reset(m)
+        s.step(nsteps)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    s.close()
+    return dict(sec=dt, updates=updates, ups=updates / dt, members=32, K=K, alg_GBs=bytes_alg / dt / 1e9)
+
+
+def adjoint_bench(fdw, torch, I, steps, warmup):
+    case, h_true = I.adjoint_case()
+    N = case.nsteps
+    rec = torch.as_tensor(case.receivers)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    # observed traces under h_true, then the misfit and its adjoint source at h = h_eps
+    s.set_coeff(torch.as_tensor(h_true, device="cuda"))
+    tr = s.record_traces(rec)
+    s.step(N)
+    d = tr.clone()
+    s.record_traces(None)
+    h = torch.as_tensor(case.h1, device="cuda")
+    s.set_coeff(h)
+    tr = s.record_traces(rec)
+    s.step(N)
+    J, tg = s.misfit(tr, d)
+    s.record_traces(None)
+    nb = fdw.lib().fdw_adjoint_workspace_bytes(s.ctx, 0, 64)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    g = torch.empty((case.ny, case.nx), dtype=torch.float64, device="cuda")
+    recd = rec.to(device="cuda", dtype=torch.int32).contiguous()
+
+    def fwd():
+        s.reset()
+        s.step(N)
+
+    def adj():
+        s._check(fdw.lib().fdw_adjoint(s.ctx, 0, fdw._ptr(recd), recd.shape[0], fdw._ptr(tg), 64, fdw._ptr(ws), nb,
+                                       fdw._ptr(g), None))
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tf = timed(fwd)
+    ta = timed(adj)
+    s.close()
+    return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, n=case.nx, nsteps=N)
+
+
+def cpu_baseline(I, budget_s=15.0):
+    import numpy as np
+
+    import oracle
+
+    n = 8192
+    case = I.point_case(n=n, nsteps=5000)
+    t0 = time.perf_counter()
+    oracle.forward_case(case, nsteps=1)
+    t1 = time.perf_counter() - t0
+    k = max(2, int(budget_s / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.forward_case(case, nsteps=k)
+    dt = time.perf_counter() - t0
+    ups = (n - 2) * (n - 2) * k / dt
+    return dict(value=ups, unit="grid-point updates/s", cores=oracle.threads(), kind="oracle",
+                sample=f"FP64 oracle, 8192x8192 point-singularity workload, first {k} of 5000 steps "
+                       f"({dt:.1f} s wall)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--skip-extra", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
+              "(the sharding design is described in the design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    from paper_2005_11931_amd import fdw
+    from paper_2005_11931_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("forward fp32 8192^2 x 5000")
+    f32 = forward_bench(fdw, torch, I, fdw.FDW_F32, args.steps, args.warmup)
+    log(json.dumps(f32))
+    nodes = f32["n"] * f32["n"]
+    K = f32["K"]
+    per_launch_bytes = 5 * 4 * nodes  # read u, du, h; write u, du (FP32 words) per streaming launch
+    avg_launch_s = f32["kernel_ms"] / 1e3 / max(f32["launches"], 1)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    traffic = load_traffic("k_step_f32_point8192_traffic.json", nodes)
+    roof = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": f"k_step<float,K={K},nodal>",
+        "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+        "launches": f32["launches"],
+        "bytes_per_launch": per_launch_bytes,
+        "effective_vs_single_step_roofline": round(f32["ups"] / (HBM_PEAK_GBS * 1e9 / 20.0), 3),
+    }
+    out = {
+        "metric": METRIC,
+        "value": round(f32["ups"], 1),
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["sec"] * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "8192x8192 point singularity h = 1 + 5 phi_eps(r), eps = 4 dx, 4 seeded humps, "
+                        "5000 leapfrog steps at CFL 0.5 with per-step energy, FP32 storage",
+            "grid": [8192, 8192],
+            "nsteps": 5000,
+            "time_block": K,
+            "segment_rows": f32["S"],
+            "energy_drift": f32["drift"],
+        },
+        "roofline": roof,
+    }
+    if not args.skip_extra:
+        log("forward fp64 8192^2 x 5000")
+        f64 = forward_bench(fdw, torch, I, fdw.FDW_F64, max(1, args.steps - 1), args.warmup)
+        log(json.dumps(f64))
+        a64 = 5 * 8 * nodes / (f64["kernel_ms"] / 1e3 / max(f64["launches"], 1)) / 1e9
+        out["fp64"] = {"value": round(f64["ups"], 1), "unit": "grid-point updates/s", "ms_per_step": round(
+            f64["sec"] * 1e3, 2), "time_block": f64["K"], "kernel_GBs": round(a64, 1),
+            "frac": round(a64 / HBM_PEAK_GBS, 4), "energy_drift": f64["drift"]}
+        torch.cuda.empty_cache()
+        log("batched family")
+        fam = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
+        log(json.dumps(fam))
+        out["batched"] = {"value": round(fam["ups"], 1), "unit": "grid-point updates/s", "members": 32,
+                          "ms_per_step": round(fam["sec"] * 1e3, 2), "time_block": fam["K"],
+                          "alg_GBs": round(fam["alg_GBs"], 1), "frac": round(fam["alg_GBs"] / HBM_PEAK_GBS, 4),
+                          "workload": "32 regularisations, eps log-spaced 0.1 .. 2dx, delta line / Heaviside jump, "
+                                      "512^2-4096^2, 2000 steps, FP32, one persistent launch"}
+        torch.cuda.empty_cache()
+        log("adjoint 2048^2 fp64 x 4000")
+        adj = adjoint_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
+        log(json.dumps(adj))
+        out["adjoint"] = {"ratio": round(adj["ratio"], 3), "forward_ms": round(adj["forward_s"] * 1e3, 2),
+                          "adjoint_ms": round(adj["adjoint_s"] * 1e3, 2),
+                          "workload": "2048x2048 FP64 receiver-misfit gradient, 4000 steps, 64 receivers, "
+                                      "checkpoints every 64 steps"}
+    if not args.skip_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(I)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

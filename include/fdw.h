@@ -160,7 +160,13 @@ int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
  *     replays it for later calls with the same shape (0 = plain launches);
  *   FDW_CFG_BATCH_MODE: for count > 1, 0 = one launch per time block covering all members,
  *     1 = one persistent cooperative launch per step_n call. */
-enum { FDW_CFG_TIME_BLOCK = 1, FDW_CFG_SEGMENT_ROWS = 2, FDW_CFG_USE_GRAPH = 3, FDW_CFG_BATCH_MODE = 4 };
+enum {
+    FDW_CFG_TIME_BLOCK = 1,
+    FDW_CFG_SEGMENT_ROWS = 2,
+    FDW_CFG_USE_GRAPH = 3,
+    FDW_CFG_BATCH_MODE = 4,
+    FDW_CFG_TIMING = 5 /* 1: bracket every stencil launch with HIP events (see fdw_kernel_time) */
+};
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
 
@@ -172,6 +178,11 @@ int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
  * steps: time steps per candidate run (0 = automatic).  best_out (host, may be NULL)
  * receives {time_block, segment_rows}. */
 int fdw_autotune(fdw_ctx* ctx, int32_t steps, int64_t* best_out);
+
+/* Instrumentation (FDW_CFG_TIMING = 1, not under graph replay): synchronise the stream and
+ * report the summed device time (ms) and the number of the streaming stencil launches made
+ * since the previous call; the counters are then cleared.  ms and launches are host pointers. */
+int fdw_kernel_time(fdw_ctx* ctx, double* ms, int64_t* launches);
 
 const char* fdw_last_error(const fdw_ctx* ctx);
 const char* fdw_status_string(int status);

@@ -76,7 +76,9 @@ struct fdw_ctx {
     int* status = nullptr;
     int* barrier = nullptr;
     double* scal = nullptr;  // small device scalars (energies read back by fdw_energy)
-    int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0;
+    int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0, timing = 0;
+    std::vector<hipEvent_t> ev_pool;  // instrumentation: start/end pairs of stencil launches
+    size_t ev_used = 0;
     int S_eff = 0;
     int64_t ctx_step = 0;
     int64_t launches = 0;
@@ -263,7 +265,20 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
         }
         return FDW_OK;
     }
+    const bool timed = c->timing && s == c->stream;
+    if (timed) {
+        while (c->ev_pool.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev_pool.push_back(e);
+        }
+        HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
+    }
     HIPCHK(c, launch_step<T>(a, K, face_mode, total, s));
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
+        c->ev_used += 2;
+    }
     return FDW_OK;
 }
 
@@ -585,6 +600,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
 void fdw_destroy(fdw_ctx* c)
 {
     if (!c) return;
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     for (auto& kv : c->graphs)
         if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
@@ -796,11 +812,31 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "batch mode must be 0 or 1");
         c->batch_mode = (int)v;
         break;
+    case FDW_CFG_TIMING:
+        if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "timing must be 0 or 1");
+        c->timing = (int)v;
+        break;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
     invalidate_graphs(c);
     for (int i = 0; i < c->count; ++i) sync_member_dev(c, i);
     return layout_for_K(c, choose_K(c), c->S_eff);
+}
+
+int fdw_kernel_time(fdw_ctx* c, double* ms, int64_t* launches)
+{
+    if (!c || !ms || !launches) return FDW_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev_pool[k], c->ev_pool[k + 1]));
+        tot += t;
+    }
+    *ms = tot;
+    *launches = (int64_t)(c->ev_used / 2);
+    c->ev_used = 0;
+    return FDW_OK;
 }
 
 int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
@@ -811,6 +847,7 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
     case FDW_CFG_SEGMENT_ROWS: return c->S_eff;
     case FDW_CFG_USE_GRAPH: return c->use_graph;
     case FDW_CFG_BATCH_MODE: return c->batch_mode;
+    case FDW_CFG_TIMING: return c->timing;
     default: return -1;
     }
 }

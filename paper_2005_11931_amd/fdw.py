@@ -27,13 +27,13 @@ _lib = ctypes.CDLL(LIB_PATH)
 FDW_F32, FDW_F64 = 0, 1
 FDW_OK, FDW_EINVAL, FDW_ECFL, FDW_ESTATE, FDW_ENOMEM, FDW_EHIP, FDW_EUNSTABLE, FDW_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 FDW_ALLOW_UNSTABLE, FDW_ALLOW_ZERO_H = 1, 2
-FDW_CFG_TIME_BLOCK, FDW_CFG_SEGMENT_ROWS, FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE = 1, 2, 3, 4
+FDW_CFG_TIME_BLOCK, FDW_CFG_SEGMENT_ROWS, FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE, FDW_CFG_TIMING = 1, 2, 3, 4, 5
 
 EXPORTED = [
     "fdw_workspace_bytes", "fdw_init", "fdw_set_coeff", "fdw_step_n", "fdw_energy", "fdw_record_traces",
     "fdw_misfit", "fdw_adjoint_workspace_bytes", "fdw_adjoint", "fdw_get_state", "fdw_set_state", "fdw_reset",
-    "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_last_error", "fdw_status_string",
-    "fdw_destroy",
+    "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_kernel_time", "fdw_last_error",
+    "fdw_status_string", "fdw_destroy",
 ]
 
 
@@ -70,6 +70,8 @@ _lib.fdw_configure.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
 _lib.fdw_get_config.argtypes = [_vp, ctypes.c_int32]
 _lib.fdw_get_config.restype = ctypes.c_int64
 _lib.fdw_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+_lib.fdw_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.fdw_kernel_time.restype = ctypes.c_int
 _lib.fdw_last_error.argtypes = [_vp]
 _lib.fdw_last_error.restype = ctypes.c_char_p
 _lib.fdw_status_string.argtypes = [ctypes.c_int]
@@ -247,6 +249,13 @@ class Solver:
     def config(self, key: int) -> int:
         return int(_lib.fdw_get_config(self.ctx, key))
 
+    def kernel_time(self) -> Tuple[float, int]:
+        """(total ms, launches) of the stencil launches since the last call (FDW_CFG_TIMING = 1)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(_lib.fdw_kernel_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
     def autotune(self, steps: int = 0) -> Tuple[int, int]:
         out = (ctypes.c_int64 * 2)()
         self._check(_lib.fdw_autotune(self.ctx, int(steps), out))
@@ -297,6 +306,7 @@ class FdwMisfit(torch.autograd.Function):
         ctx.solver = solver
         ctx.receivers = receivers
         ctx.ckpt = ckpt_every
+        ctx.h_dtype = h.dtype
         ctx.save_for_backward(g)
         solver.record_traces(None)
         return J
@@ -306,4 +316,4 @@ class FdwMisfit(torch.autograd.Function):
         (g,) = ctx.saved_tensors
         tg = g * grad_out.to(torch.float64)
         grad_h = ctx.solver.adjoint(ctx.receivers, tg, ckpt_every=ctx.ckpt)
-        return grad_h, None, None, None, None
+        return grad_h.to(ctx.h_dtype), None, None, None, None

@@ -1,0 +1,211 @@
+"""GPU adjoint (a7-a9) against the FP64 oracle's adjoint and against central finite
+differences of the GPU forward, through the C-ABI; FdwMisfit autograd wrapper.
+
+Bar: gradient within 1e-6 relative (FP64) of the oracle and of central differences.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_11931_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _fdw():
+    from paper_2005_11931_amd import fdw
+
+    return fdw
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(nx=96, ny=80, N=150, R=12, seed=3, face=False):
+    rng = np.random.default_rng(seed)
+    x, y, X, Y = I.mesh(nx, ny)
+    h1 = 1.0 + 2.0 * I.gaussian_1d(X, 0.1) + 0.1 * rng.uniform(size=(ny, nx))
+    h2 = (0.8 + 0.3 * rng.uniform(size=(ny, nx))) if face else None
+    u0 = I.zero_ring(np.exp(-((X - 0.3) ** 2 + Y**2) / 0.02))
+    u1 = I.zero_ring(0.2 * np.exp(-((X + 0.2) ** 2 + (Y - 0.1) ** 2) / 0.05))
+    dx, dy = 2.0 / (nx - 1), 2.0 / (ny - 1)
+    hm = max(h1.max(), h2.max() if face else 0)
+    tau = 0.45 / math.sqrt(hm * (1 / dx**2 + 1 / dy**2))
+    cols = rng.choice(np.arange(1, nx - 1), size=R, replace=False)
+    rows = rng.integers(1, ny - 1, size=R)
+    rec = np.stack([cols, rows], axis=1).astype(np.int32)
+    case = I.Case("adj", nx, ny, -1, 1, -1, 1, tau, N, h1, h2, u0, u1, receivers=rec)
+    d = rng.normal(size=(N + 1, R)) * 0.02
+    return case, d
+
+
+@pytest.mark.parametrize("ck", [1, 7, 16, 64, 1000])
+def test_adjoint_vs_oracle_fp64(ck):
+    import torch
+
+    fdw = _fdw()
+    case, d = _problem()
+    _say("adjoint fp64 ck", ck)
+    ref = oracle.forward_case(case)
+    tg = 2.0 * (ref["traces"] - d)
+    gref = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, None, case.u0, case.u1, case.nsteps,
+                          case.receivers, tg, ckpt_every=ck)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    g = s.adjoint(torch.as_tensor(case.receivers), torch.as_tensor(tg), ckpt_every=ck).cpu().numpy()
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    _say("rel", rel)
+    assert rel <= 1e-9
+    assert np.abs(g - gref).max() <= 1e-9 * np.abs(gref).max()
+    # the forward state of the context is untouched by the adjoint
+    assert s.steps_taken() == 0
+    s.close()
+
+
+def test_adjoint_separate_h1_h2_vs_oracle():
+    import torch
+
+    fdw = _fdw()
+    case, d = _problem(nx=71, ny=103, N=90, face=True, seed=9)
+    _say("adjoint face layout")
+    ref = oracle.forward_case(case)
+    tg = 2.0 * (ref["traces"] - d)
+    g1r, g2r = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, case.h2, case.u0, case.u1,
+                              case.nsteps, case.receivers, tg, ckpt_every=10, separate=True)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    g1, g2 = s.adjoint(torch.as_tensor(case.receivers), torch.as_tensor(tg), ckpt_every=10, separate=True)
+    for g, gr in ((g1, g1r), (g2, g2r)):
+        g = g.cpu().numpy()
+        assert np.linalg.norm(g - gr) <= 1e-9 * np.linalg.norm(gr)
+    # summed form equals the sum of the parts
+    gs = s.adjoint(torch.as_tensor(case.receivers), torch.as_tensor(tg), ckpt_every=10).cpu().numpy()
+    assert np.linalg.norm(gs - (g1r + g2r)) <= 1e-9 * np.linalg.norm(g1r + g2r)
+    s.close()
+
+
+def test_adjoint_fp32_reported():
+    import torch
+
+    fdw = _fdw()
+    case, d = _problem(seed=4)
+    _say("adjoint fp32")
+    ref = oracle.forward_case(case)
+    tg = 2.0 * (ref["traces"] - d)
+    gref = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, None, case.u0, case.u1, case.nsteps,
+                          case.receivers, tg, ckpt_every=16)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+    g = s.adjoint(torch.as_tensor(case.receivers), torch.as_tensor(tg), ckpt_every=16).cpu().numpy()
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    _say("fp32 adjoint rel", rel)
+    assert rel <= 1e-3
+    s.close()
+
+
+def test_adjoint_vs_central_fd_gpu():
+    """16 seeded directions v = G/max|G| (correlation length 0.1), delta = 1e-5."""
+    import torch
+
+    fdw = _fdw()
+    n, N = 256, 400
+    case, h_true = I.adjoint_case(n=n, nsteps=N, nrecv=32)
+    _say("fd gpu", n, N)
+    rec = torch.as_tensor(case.receivers)
+    td = torch.float64
+
+    def loss(h, d=None, want_traces=False):
+        s = fdw.solver_for_case(I.Case(**{**case.__dict__, "h1": h}), dtype=fdw.FDW_F64)
+        tr = s.record_traces(rec)
+        s.step(N)
+        out = tr.clone()
+        if d is None:
+            s.close()
+            return out
+        J, g = s.misfit(tr, d)
+        val = J.item()
+        s.close()
+        return (val, g) if want_traces else val
+
+    d = loss(h_true)
+    J0, tg = loss(case.h1, d, want_traces=True)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    g = s.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+    s.close()
+    worst = 0.0
+    for k in range(16):
+        v = I.fd_direction(n, k)
+        delta = 1e-5
+        fd = (loss(case.h1 + delta * v, d) - loss(case.h1 - delta * v, d)) / (2 * delta)
+        ad = float(np.sum(g * v))
+        worst = max(worst, abs(fd - ad) / abs(fd))
+    _say("worst fd rel", worst)
+    assert worst <= 1e-6
+
+
+def test_fdw_misfit_autograd():
+    import torch
+
+    fdw = _fdw()
+    case, d = _problem(nx=64, ny=64, N=80, seed=12)
+    _say("autograd")
+    p = fdw.problem_from_case(case, fdw.FDW_F64)
+    u0 = torch.as_tensor(case.u0, device="cuda")
+    solver = fdw.Solver([p], [u0], [torch.as_tensor(case.u1, device="cuda")])
+    h = torch.as_tensor(case.h1, device="cuda").clone().requires_grad_(True)
+    rec = torch.as_tensor(case.receivers)
+    dd = torch.as_tensor(d, device="cuda")
+    J = fdw.FdwMisfit.apply(h, solver, rec, dd, 8)
+    J.backward()
+    ref = oracle.forward_case(case)
+    Jref = oracle.misfit(ref["traces"], d)
+    gref = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, None, case.u0, case.u1, case.nsteps,
+                          case.receivers, 2.0 * (ref["traces"] - d), ckpt_every=8)
+    assert abs(J.item() - Jref) <= 1e-12 * abs(Jref)
+    assert np.linalg.norm(h.grad.cpu().numpy() - gref) <= 1e-9 * np.linalg.norm(gref)
+    solver.close()
+
+
+def test_adjoint_workload_full_size_fd():
+    """The 2048^2 FP64, 4000-step receiver-misfit gradient with checkpoints every 64 steps,
+    checked against central differences of the GPU forward on 16 seeded directions."""
+    import torch
+
+    fdw = _fdw()
+    case, h_true = I.adjoint_case()
+    N = case.nsteps
+    rec = torch.as_tensor(case.receivers)
+    _say("full-size adjoint", case.nx, N)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+
+    def traces_for(h):
+        s.set_coeff(torch.as_tensor(h, device="cuda"))
+        tr = s.record_traces(rec)
+        s.step(N)
+        out = tr.clone()
+        s.record_traces(None)
+        return out
+
+    d = traces_for(h_true)
+
+    def loss(h):
+        tr = traces_for(h)
+        J, _ = s.misfit(tr, d, want_grad=False)
+        return J.item()
+
+    tr0 = traces_for(case.h1)
+    J0, tg = s.misfit(tr0, d)
+    s.set_coeff(torch.as_tensor(case.h1, device="cuda"))
+    g = s.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+    worst = 0.0
+    for k in range(16):
+        v = I.fd_direction(case.nx, k)
+        delta = 1e-5
+        fd = (loss(case.h1 + delta * v) - loss(case.h1 - delta * v)) / (2 * delta)
+        ad = float(np.sum(g * v))
+        worst = max(worst, abs(fd - ad) / abs(fd))
+        _say("dir", k, fd, ad, abs(fd - ad) / abs(fd))
+    assert worst <= 1e-6
+    s.close()

@@ -1,0 +1,136 @@
+"""Batched family of regularisations (a10): one launch per time block over all members, and
+one persistent cooperative launch per step_n call.  Each member must equal its own
+single-member solve bit for bit, and the oracle within the FP64 / FP32 bars."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_11931_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _fdw():
+    from paper_2005_11931_amd import fdw
+
+    return fdw
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _small_family(count=6, nsteps=90, sizes=(67, 131, 200)):
+    return I.family(count=count, nsteps=nsteps, sizes=sizes)
+
+
+def _states(s):
+    return [tuple(t.cpu().numpy() for t in s.get_state(m)[:2]) for m in range(s.count)]
+
+
+def _single(case, dtype, n, K=0, energy=False):
+    fdw = _fdw()
+    s = fdw.solver_for_case(case, dtype=dtype)
+    if K:
+        s.configure(fdw.FDW_CFG_TIME_BLOCK, K)
+    e = s.step(n, energy=energy)
+    u, du, _ = s.get_state()
+    out = (u.cpu().numpy(), du.cpu().numpy(), None if e is None else e[0].cpu().numpy())
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "f64"])
+def test_batched_equals_single_and_oracle(dtype_name):
+    fdw = _fdw()
+    dt = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
+    fam = _small_family()
+    N = fam[0].nsteps
+    _say("batched", dtype_name)
+    for K in (1, 3, 4):
+        s = fdw.family_solver(fam, dtype=dt)
+        s.configure(fdw.FDW_CFG_TIME_BLOCK, K)
+        E = s.step(N, energy=True).cpu().numpy()
+        st = _states(s)
+        s.close()
+        for m, case in enumerate(fam):
+            u1, du1, e1 = _single(case, dt, N, K=K, energy=True)
+            assert np.array_equal(st[m][0], u1) and np.array_equal(st[m][1], du1), (K, m)
+            assert np.abs(E[m] - e1).max() <= 1e-13 * abs(e1[0])
+            ref = oracle.forward_case(case, want_energy=True)
+            if dt == fdw.FDW_F64:
+                assert np.abs(st[m][0] - ref["u_cur"]).max() <= 1e-12
+                assert np.abs(E[m] - ref["energy"]).max() <= 1e-12 * ref["energy"][0]
+            else:
+                assert np.abs(st[m][0] - ref["u_cur"]).max() <= 1e-5 * np.abs(ref["u_cur"]).max()
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "f64"])
+def test_persistent_equals_per_block_launches(dtype_name):
+    fdw = _fdw()
+    dt = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
+    fam = _small_family(count=8, nsteps=203)
+    _say("persistent", dtype_name)
+    for K in (1, 2, 4):
+        a = fdw.family_solver(fam, dtype=dt)
+        a.configure(fdw.FDW_CFG_TIME_BLOCK, K)
+        a.step(203)
+        sa = _states(a)
+        a.close()
+        b = fdw.family_solver(fam, dtype=dt)
+        b.configure(fdw.FDW_CFG_TIME_BLOCK, K)
+        b.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+        b.step(1)
+        b.step(150)
+        b.step(52)
+        sb = _states(b)
+        b.close()
+        for m in range(len(fam)):
+            assert np.array_equal(sa[m][0], sb[m][0]) and np.array_equal(sa[m][1], sb[m][1]), (K, m)
+
+
+def test_member_reset_mid_run():
+    """A member returned to step 0 restarts (start step) while the others continue."""
+    fdw = _fdw()
+    fam = _small_family(count=3, nsteps=100)
+    _say("reset mid-run")
+    s = fdw.family_solver(fam, dtype=fdw.FDW_F64)
+    s.step(30)
+    s.reset(1)
+    s.step(40)
+    assert [s.steps_taken(m) for m in range(3)] == [70, 40, 70]
+    st = _states(s)
+    s.close()
+    for m, n in ((0, 70), (1, 40), (2, 70)):
+        ref = oracle.forward_case(fam[m], nsteps=n)["u_cur"]
+        assert np.abs(st[m][0] - ref).max() <= 1e-12, m
+
+
+def test_full_family_launch_configuration():
+    """The 32-member family (512^2 .. 4096^2, FP32) in the benchmark's launch configuration:
+    after 24 steps every member equals its single-member solve bit for bit; the smallest
+    members are also run for the full 2000 steps against the oracle."""
+    import torch
+
+    fdw = _fdw()
+    fam = I.family()
+    _say("full family")
+    s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
+    s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+    s.step(24)
+    st = _states(s)
+    s.close()
+    torch.cuda.empty_cache()
+    for m, case in enumerate(fam):
+        u1, du1, _ = _single(case, fdw.FDW_F32, 24)
+        assert np.array_equal(st[m][0], u1) and np.array_equal(st[m][1], du1), m
+    for m in (0, 28):  # 512^2 jump member, 512^2 smallest-eps delta member
+        case = fam[m]
+        u, _, _ = _single(case, fdw.FDW_F32, case.nsteps)
+        ref = oracle.forward_case(case)["u_cur"]
+        rel = np.abs(u - ref).max() / np.abs(ref).max()
+        _say("member", m, "fp32 rel", rel)
+        assert rel <= 1e-5
