@@ -92,17 +92,17 @@ size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count);
 int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t ws_bytes,
              const void* const* u0, const void* const* u1, void* hip_stream, fdw_ctx** out);
 
-/* Set member m's coefficient (a1: face coefficients and the stability check).
+/* Set member m's coefficient (face coefficients and the stability check).
  * h1: device [ny][nx] nodal h1; h2: device nodal h2, or NULL when h2 = h1 (the physical
  * model h_1 = h_2 = h; a faster nodal layout is used).  The values are validated (finite,
  * > 0, or >= 0 with FDW_ALLOW_ZERO_H) and the CFL bound is checked; both read one small
  * result back to the host, so this call synchronises the stream.  Resets member m to n = 0. */
 int fdw_set_coeff(fdw_ctx* ctx, int32_t member, const void* h1, const void* h2);
 
-/* Advance every member by n >= 0 steps (a2 start step when a member is at n = 0, then a3
- * leapfrog steps).  energy_dev: NULL, or device double [count][n] receiving
- * E^{k+1/2} for k = n_cur .. n_cur+n-1 of each member (a5).  Traces registered with
- * fdw_record_traces are written as the steps are taken (a7). */
+/* Advance every member by n >= 0 steps (the Taylor start step when a member is at n = 0,
+ * then leapfrog steps).  energy_dev: NULL, or device double [count][n] receiving
+ * E^{k+1/2} for k = n_cur .. n_cur+n-1 of each member.  Traces registered with
+ * fdw_record_traces are written as the steps are taken. */
 int fdw_step_n(fdw_ctx* ctx, int64_t n, double* energy_dev);
 
 /* E^{n-1/2} of each member's current pair (u^{n-1}, u^n), into host double [count].
@@ -116,18 +116,18 @@ int fdw_energy(fdw_ctx* ctx, double* energy_host);
  * R = 0 (or traces = NULL) stops recording. */
 int fdw_record_traces(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, void* traces);
 
-/* Misfit of a7: J = sum_{k=0}^{rows-1} sum_r (traces[k][r] - d[k][r])^2 in double, and the
+/* Receiver misfit: J = sum_{k=0}^{rows-1} sum_r (traces[k][r] - d[k][r])^2 in double, and the
  * adjoint source trace_grad[k][r] = 2 (traces - d) (double, may be NULL).  traces is in the
  * storage type of member m, d is double; all device; J_dev is a device double. */
 int fdw_misfit(fdw_ctx* ctx, int32_t member, const void* traces, const double* d, int64_t rows, int32_t R,
                double* J_dev, double* trace_grad);
 
 /* Device workspace (bytes) fdw_adjoint needs for member m with checkpoints every
- * ckpt_every steps (a9). */
+ * ckpt_every steps. */
 size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t ckpt_every);
 
 /* Gradient with respect to the nodal coefficient(s) of a loss L of the traces u^k_r,
- * k = 0..N (a8, a9): the forward recurrence is replayed from member m's initial data
+ * k = 0..N: the forward recurrence is replayed from member m's initial data
  * storing the state every ckpt_every steps, then the transposed (reverse leapfrog)
  * recurrence runs backwards, each segment being reconstructed from its checkpoint by time
  * reversal.  trace_grad: device double [N+1][R] = dL/du^k at the receivers;
@@ -138,7 +138,7 @@ size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t c
 int fdw_adjoint(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, const double* trace_grad,
                 int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes, double* grad_h1, double* grad_h2);
 
-/* Snapshot / resume (a6): copy member m's state (u^n, du^n = u^n - u^{n-1}) to device
+/* Snapshot / resume: copy member m's state (u^n, du^n = u^n - u^{n-1}) to device
  * buffers [ny][nx] in the storage type and its step counter to *n (host).  du is all zeros
  * at n = 0.  u and du may be NULL. */
 int fdw_get_state(fdw_ctx* ctx, int32_t member, void* u, void* du, int64_t* n);
@@ -154,7 +154,8 @@ int fdw_reset(fdw_ctx* ctx, int32_t member);
 int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
 
 /* Execution configuration (tuning; results do not depend on it, bit for bit):
- *   FDW_CFG_TIME_BLOCK: time steps per stencil launch, 1..8 (0 = automatic);
+ *   FDW_CFG_TIME_BLOCK: time steps per stencil launch: 1..8 for float with 2 columns per lane, 1..6
+ *     with 4, 1..4 for double (0 = automatic);
  *   FDW_CFG_SEGMENT_ROWS: rows per streaming work item, 8..4096 (0 = automatic);
  *   FDW_CFG_USE_GRAPH: 1 captures the launch sequence of a step_n call in a hipGraph and
  *     replays it for later calls with the same shape (0 = plain launches);
@@ -165,18 +166,23 @@ enum {
     FDW_CFG_SEGMENT_ROWS = 2,
     FDW_CFG_USE_GRAPH = 3,
     FDW_CFG_BATCH_MODE = 4,
-    FDW_CFG_TIMING = 5 /* 1: bracket every stencil launch with HIP events (see fdw_kernel_time) */
+    FDW_CFG_TIMING = 5, /* 1: bracket every stencil launch with HIP events (see fdw_kernel_time) */
+    FDW_CFG_LANE_COLUMNS = 6, /* grid columns per lane of the streaming kernels: 2 or 4 (float), 2 (double); 0 = default */
+    FDW_CFG_ADJ_TIME_BLOCK = 7,  /* reverse steps per launch of the adjoint sweep, 1..4 (0 = 2) */
+    FDW_CFG_ADJ_LANE_COLUMNS = 8 /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
+                                    0 = default (2 for float, 1 for double) */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
 
 /* Autotune the execution configuration for this context: times short runs of the candidate
- * (time block, segment rows) pairs on the context's stream, picks the fastest (ties go to
- * the smaller time block) and applies it.  The member states are saved and restored.
- * The choice is cached in the file named by the FDW_AUTOTUNE_CACHE environment variable
- * (if set) under a key of (device arch, storage type, nx, ny, layout, count).
- * steps: time steps per candidate run (0 = automatic).  best_out (host, may be NULL)
- * receives {time_block, segment_rows}. */
+ * (columns per lane, time block, segment rows) triples on the context's stream, picks the
+ * fastest (a larger time block must win by 2%) and applies it.  Every member must be at
+ * step 0 (FDW_ESTATE otherwise) and is returned to step 0.  The choice is cached in the
+ * file named by the FDW_AUTOTUNE_CACHE environment variable (if set) under a key of
+ * (device arch, storage type, member sizes and layouts).  steps: time steps per candidate
+ * run (0 = automatic).  best_out (host, may be NULL) receives
+ * {time_block, segment_rows, lane_columns}. */
 int fdw_autotune(fdw_ctx* ctx, int32_t steps, int64_t* best_out);
 
 /* Instrumentation (FDW_CFG_TIMING = 1, not under graph replay): synchronise the stream and

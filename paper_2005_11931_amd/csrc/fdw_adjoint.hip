@@ -21,99 +21,26 @@
 // rows in registers, DPP lane exchange); the gradient of a node collects the K levels in
 // registers and is added to the FP64 accumulator plane once per launch.
 #include "fdw_internal.h"
+#include "fdw_stream.h"
 
 #include <hip/hip_runtime.h>
 
 namespace fdw {
 
-__device__ __forceinline__ int adj_from_left_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int adj_from_right_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
-__device__ __forceinline__ float adj_from_left(float v)
-{
-    return __builtin_bit_cast(float, adj_from_left_i(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ float adj_from_right(float v)
-{
-    return __builtin_bit_cast(float, adj_from_right_i(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double adj_from_left(double v)
-{
-    long long b = __builtin_bit_cast(long long, v);
-    int lo = adj_from_left_i((int)(b & 0xffffffffLL));
-    int hi = adj_from_left_i((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double adj_from_right(double v)
-{
-    long long b = __builtin_bit_cast(long long, v);
-    int lo = adj_from_right_i((int)(b & 0xffffffffLL));
-    int hi = adj_from_right_i((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Same operation order as the forward point update (fdw_kernels.hip), so that the reverse
-// reconstruction uses bit-identical operator values.
-template <typename T>
-__device__ __forceinline__ T adj_flux(T uc, T ue, T uw, T un, T us, T fxe, T fxw, T fyn, T fys, T ax, T ay)
-{
-    T pe = fxe * (ue - uc);
-    T pw = fxw * (uw - uc);
-    T pn = fyn * (un - uc);
-    T ps = fys * (us - uc);
-    T sx = pe + pw;
-    T sy = pn + ps;
-    return __builtin_fma(ax, sx, ay * sy);
-}
-template <>
-__device__ __forceinline__ float adj_flux<float>(float uc, float ue, float uw, float un, float us, float fxe, float fxw,
-                                                 float fyn, float fys, float ax, float ay)
-{
-    float pe = fxe * (ue - uc);
-    float pw = fxw * (uw - uc);
-    float pn = fyn * (un - uc);
-    float ps = fys * (us - uc);
-    float sx = pe + pw;
-    float sy = pn + ps;
-    return __builtin_fmaf(ax, sx, ay * sy);
-}
-
-template <typename T, int C>
-struct alignas(sizeof(T) * C) APack {
-    T v[C];
-};
-template <typename T, int C>
-__device__ __forceinline__ void aload(const T* __restrict__ p, T (&o)[C])
-{
-    APack<T, C> q = *reinterpret_cast<const APack<T, C>*>(p);
-#pragma unroll
-    for (int c = 0; c < C; ++c) o[c] = q.v[c];
-}
-template <typename T, int C>
-__device__ __forceinline__ void astore(T* __restrict__ p, const T (&in)[C])
-{
-    APack<T, C> q;
-#pragma unroll
-    for (int c = 0; c < C; ++c) q.v[c] = in[c];
-    *reinterpret_cast<APack<T, C>*>(p) = q;
-}
-
-template <typename T>
-struct ALanes;
-template <>
-struct ALanes<float> {
-    static constexpr int C = 4;
-};
-template <>
-struct ALanes<double> {
-    static constexpr int C = 2;
-};
-
-template <typename T, int K, int FACE>
+// One reverse work item (strip x segment, K levels, C columns per lane).  Level s (s = 1..K)
+// turns the time-(m-s+1) quadruple (u, du, lam, mu) into the time-(m-s) one at row
+// r = j - s.  u^{m-s} is produced one row ahead (pointwise from level s-1), so that the
+// operator on u^{m-s} and on lam^{m-s+1} can be written in flux form like the forward kernel
+// (x fluxes per face, y flux carried from the row above).  The gradient terms are products
+// of the face differences, Px = (u_{c+1}-u_c)(lam_{c+1}-lam_c), each shared by the face's two
+// nodes; a node collects its K levels in registers and its accumulator plane is updated once
+// per launch.
+template <typename T, int K, int C, int FACE>
 __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs a)
 {
-    constexpr int C = ALanes<T>::C;
     constexpr int Hx = ((K + C - 1) / C) * C;
     constexpr int Wv = kWaveSize * C - 2 * Hx;
+    constexpr int U = RowUnroll<K>::U;
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (wave >= a.waves) return;
@@ -124,260 +51,274 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     const int cb = strip * Wv - Hx + lane * C;
     const bool lane_live = (cb >= 0) && (cb < ld);
     const bool lane_owned = lane_live && (lane * C >= Hx) && (lane * C < Hx + Wv);
-    bool colin[C];
+    T colm[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) colin[c] = (cb + c >= 1) && (cb + c <= nx - 2);
+    for (int c = 0; c < C; ++c) colm[c] = ((cb + c >= 1) && (cb + c <= nx - 2)) ? T(1) : T(0);
     const int r0 = seg * a.seg_rows;
     const int r1 = min(r0 + a.seg_rows, ny);
-
-    const T* __restrict__ uin = (const T*)a.uin;
-    const T* __restrict__ din = (const T*)a.din;
-    const T* __restrict__ lin = (const T*)a.lin;
-    const T* __restrict__ mi = (const T*)a.min;
-    T* __restrict__ uout = (T*)a.uout;
-    T* __restrict__ dout = (T*)a.dout;
-    T* __restrict__ lout = (T*)a.lout;
-    T* __restrict__ mout = (T*)a.mout;
-    const T* __restrict__ hp = (const T*)a.h;
-    const T* __restrict__ hyp = (const T*)a.hy;
     const T ax = (T)a.ax, ay = (T)a.ay;
     const double axd = a.ax, ayd = a.ay;
     const bool split = (a.g2 != a.g1);
 
-    // W[s-1]: u^{m-s} rows (r-1, r, r+1) for level s (s = 1..K)
-    // D[s], LM[s], MU[s]: level s increments / adjoint / adjoint increments (s = 0..K-1)
-    T W[K][3][C];
-    T D[K][2][C];
-    T LA[K][3][C];
-    T MU[K][2][C];
-    constexpr int HR = FACE ? 1 : (K + 2);
-    constexpr int XR = FACE ? (K + 1) : 1;
-    constexpr int YR = FACE ? (K + 2) : 1;
-    T Hn[HR][C + 2];
-    T FX[XR][C + 1];
-    T FY[YR][C];
-    double GX[K][C], GY[K][C];  // gradient accumulators: GX[s-1] is row j - s
-#pragma unroll
-    for (int s = 0; s < K; ++s)
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            W[s][0][c] = W[s][1][c] = W[s][2][c] = T(0);
-            D[s][0][c] = D[s][1][c] = T(0);
-            LA[s][0][c] = LA[s][1][c] = LA[s][2][c] = T(0);
-            MU[s][0][c] = MU[s][1][c] = T(0);
-            GX[s][c] = GY[s][c] = 0.0;
-        }
-#pragma unroll
-    for (int q = 0; q < HR; ++q)
-#pragma unroll
-        for (int c = 0; c < C + 2; ++c) Hn[q][c] = T(0);
-#pragma unroll
-    for (int q = 0; q < XR; ++q)
-#pragma unroll
-        for (int c = 0; c < C + 1; ++c) FX[q][c] = T(0);
-#pragma unroll
-    for (int q = 0; q < YR; ++q)
-#pragma unroll
-        for (int c = 0; c < C; ++c) FY[q][c] = T(0);
+    const int jb = r0 - K;
+    const int jbase = max(jb, 0);
+    const size_t base_el = (size_t)jbase * ld;
+    const size_t span = (size_t)(ny - jbase) * ld * sizeof(T);
+    const unsigned int nbytes = (unsigned int)min(span, (size_t)kBufferOutOfRange - 16);
+    const __amdgpu_buffer_rsrc_t ru = plane_rsrc((const T*)a.uin + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rd = plane_rsrc((const T*)a.din + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rl = plane_rsrc((const T*)a.lin + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rm = plane_rsrc((const T*)a.min + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rh = plane_rsrc((const T*)a.h + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rhy = plane_rsrc((const T*)(FACE ? a.hy : a.h) + base_el, nbytes);
+    const unsigned int row_bytes = (unsigned int)(ld * (int)sizeof(T));
+    const unsigned int lane_col = lane_live ? (unsigned int)(cb * (int)sizeof(T)) : kBufferOutOfRange;
+    // gradient accumulator planes (double), read through buffers as well
+    const size_t gspan = (size_t)(ny - jbase) * ld * sizeof(double);
+    const unsigned int gbytes = (unsigned int)min(gspan, (size_t)kBufferOutOfRange - 16);
+    const __amdgpu_buffer_rsrc_t rg1 = plane_rsrc(a.g1 + base_el, gbytes);
+    const __amdgpu_buffer_rsrc_t rg2 = plane_rsrc(a.g2 + base_el, gbytes);
+    const unsigned int grow_bytes = (unsigned int)(ld * (int)sizeof(double));
+    const unsigned int glane_col = lane_owned ? (unsigned int)(cb * (int)sizeof(double)) : kBufferOutOfRange;
+    T* __restrict__ uout = (T*)a.uout;
+    T* __restrict__ dout = (T*)a.dout;
+    T* __restrict__ lout = (T*)a.lout;
+    T* __restrict__ mout = (T*)a.mout;
 
-    for (int j = r0 - K; j < r1 + K; ++j) {
-        T lu[C], ldd[C], ll[C], lm[C], lh[C], lhy[C];
-        const bool rl = lane_live && (j >= 0) && (j < ny);
-        if (rl) {
-            const size_t off = (size_t)j * ld + cb;
-            aload<T, C>(uin + off, lu);
-            aload<T, C>(din + off, ldd);
-            aload<T, C>(lin + off, ll);
-            aload<T, C>(mi + off, lm);
-            aload<T, C>(hp + off, lh);
-            if (FACE) aload<T, C>(hyp + off, lhy);
-        } else {
+    T Ur[K + 1][2][C];  // u^{m-s}, rows by parity (level s >= 1 runs one row ahead)
+    T Dr[K][2][C];      // du^{m-s}
+    T Lr[K][2][C];      // lam^{m-s}
+    T Mr[K][2][C];      // mu^{m-s}
+    T Gu[K][C];         // y flux of u^{m-s} below row r (level s stores at s-1)
+    T Gl[K][C];         // y flux of lam^{m-s+1} below row r
+    double Py[K][C];    // y face products below row r
+    double GX[K][C], GY[K][C];  // gradient of rows j-1 .. j-K (by row modulo K)
+    T FXr[K][C], FYr[K][C];
+    T hprev[C], hyprev[C];
+    T bu[2][C], bd[2][C], bl[2][C], bm[2][C], bh[2][C], bhy[2][C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) lu[c] = ldd[c] = ll[c] = lm[c] = lh[c] = lhy[c] = T(0);
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int t = 0; t <= K; ++t) Ur[t][0][c] = Ur[t][1][c] = T(0);
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            Dr[t][0][c] = Dr[t][1][c] = Lr[t][0][c] = Lr[t][1][c] = Mr[t][0][c] = Mr[t][1][c] = T(0);
+            Gu[t][c] = Gl[t][c] = T(0);
+            Py[t][c] = GX[t][c] = GY[t][c] = 0.0;
+            FXr[t][c] = FYr[t][c] = T(0);
         }
-        const bool jin = (j >= 1) && (j <= ny - 2);
-        // level 0 rings
+        hprev[c] = hyprev[c] = T(0);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            D[0][0][c] = D[0][1][c];
-            D[0][1][c] = ldd[c];
-            LA[0][0][c] = LA[0][1][c];
-            LA[0][1][c] = LA[0][2][c];
-            LA[0][2][c] = ll[c];
-            MU[0][0][c] = MU[0][1][c];
-            MU[0][1][c] = lm[c];
-            // newest row of level 1's u: u^{m-1}(j) = u^m(j) - du^m(j)
-            W[0][0][c] = W[0][1][c];
-            W[0][1][c] = W[0][2][c];
-            W[0][2][c] = (jin && colin[c]) ? (lu[c] - ldd[c]) : T(0);
-        }
-        if (FACE) {
-#pragma unroll
-            for (int q = 0; q < XR - 1; ++q)
-#pragma unroll
-                for (int c = 0; c < C + 1; ++c) FX[q][c] = FX[q + 1][c];
-            FX[XR - 1][0] = adj_from_left(lh[C - 1]);
-#pragma unroll
-            for (int c = 0; c < C; ++c) FX[XR - 1][c + 1] = lh[c];
-#pragma unroll
-            for (int q = 0; q < YR - 1; ++q)
-#pragma unroll
-                for (int c = 0; c < C; ++c) FY[q][c] = FY[q + 1][c];
-#pragma unroll
-            for (int c = 0; c < C; ++c) FY[YR - 1][c] = lhy[c];
-        } else {
-#pragma unroll
-            for (int q = 0; q < HR - 1; ++q)
-#pragma unroll
-                for (int c = 0; c < C + 2; ++c) Hn[q][c] = Hn[q + 1][c];
-            Hn[HR - 1][0] = adj_from_left(lh[C - 1]);
-            Hn[HR - 1][C + 1] = adj_from_right(lh[0]);
-#pragma unroll
-            for (int c = 0; c < C; ++c) Hn[HR - 1][c + 1] = lh[c];
-        }
+        for (int q = 0; q < 2; ++q) bu[q][c] = bd[q][c] = bl[q][c] = bm[q][c] = bh[q][c] = bhy[q][c] = T(0);
+    }
+    auto load_row = [&](int j, T (&u)[C], T (&d)[C], T (&l)[C], T (&m)[C], T (&h)[C], T (&hy)[C]) {
+        const unsigned int off = (unsigned int)(j - jbase) * row_bytes + lane_col;
+        buffer_row<T, C>(ru, off, u);
+        buffer_row<T, C>(rd, off, d);
+        buffer_row<T, C>(rl, off, l);
+        buffer_row<T, C>(rm, off, m);
+        buffer_row<T, C>(rh, off, h);
+        if (FACE) buffer_row<T, C>(rhy, off, hy);
+    };
+    load_row(jb, bu[0], bd[0], bl[0], bm[0], bh[0], bhy[0]);
+    const int nblk = (r1 + K - jb + U - 1) / U;
 
+    for (int blk = 0; blk < nblk; ++blk) {
 #pragma unroll
-        for (int s = 1; s <= K; ++s) {
-            const int r = j - s;
-            const bool rin = (r >= 1) && (r <= ny - 2);
-            const bool rown = (r >= r0) && (r < r1);
-            const int64_t n = a.n_top - s;  // time index of this level's forward state
-            const double w = (n == 0) ? 0.5 : 1.0;
-            // u^{n} rows r-1..r+1 (W[s-1]); lam^{n+1} rows r-1..r+1 (LA[s-1])
-            const T uL = adj_from_left(W[s - 1][1][C - 1]);
-            const T uR = adj_from_right(W[s - 1][1][0]);
-            const T lL = adj_from_left(LA[s - 1][1][C - 1]);
-            const T lR = adj_from_right(LA[s - 1][1][0]);
-            T nd[C], nl[C], nm[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                T fxe, fxw, fyn, fys;
+        for (int s = 0; s < U; ++s) {
+            const int j = jb + blk * U + s;
+            const int pb = s & 1;
+            load_row(j + 1, bu[pb ^ 1], bd[pb ^ 1], bl[pb ^ 1], bm[pb ^ 1], bh[pb ^ 1], bhy[pb ^ 1]);
+            // gradient accumulator of the row completed at the end of this iteration
+            double g1old[C], g2old[C];
+            {
+                const unsigned int goff = (unsigned int)(j - K - jbase) * grow_bytes + glane_col;
+                buffer_row<double, C>(rg1, goff, g1old);
+                if (split) buffer_row<double, C>(rg2, goff, g2old);
+            }
+            // coefficient faces of row j-1
+            {
+                const int q = pmod(s - 1, K);
                 if (FACE) {
-                    fxe = FX[K - s][c + 1];
-                    fxw = FX[K - s][c];
-                    fyn = FY[K + 1 - s][c];
-                    fys = FY[K - s][c];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        FXr[q][c] = hprev[c];
+                        FYr[q][c] = hyprev[c];
+                        hprev[c] = bh[pb][c];
+                        hyprev[c] = bhy[pb][c];
+                    }
                 } else {
-                    const int q = K + 1 - s;
-                    const T hc = Hn[q][c + 1];
-                    fxe = hc + Hn[q][c + 2];
-                    fxw = Hn[q][c] + hc;
-                    fyn = hc + Hn[q + 1][c + 1];
-                    fys = Hn[q - 1][c + 1] + hc;
-                }
-                const T uc = W[s - 1][1][c];
-                const T ue = (c < C - 1) ? W[s - 1][1][c + 1] : uR;
-                const T uw = (c > 0) ? W[s - 1][1][c - 1] : uL;
-                const T un = W[s - 1][2][c];
-                const T us = W[s - 1][0][c];
-                const T lc = LA[s - 1][1][c];
-                const T le = (c < C - 1) ? LA[s - 1][1][c + 1] : lR;
-                const T lw = (c > 0) ? LA[s - 1][1][c - 1] : lL;
-                const T ln = LA[s - 1][2][c];
-                const T ls = LA[s - 1][0][c];
-                const bool in = rin && colin[c];
-                const T Lu = adj_flux<T>(uc, ue, uw, un, us, fxe, fxw, fyn, fys, ax, ay);
-                nd[c] = in ? (D[s - 1][0][c] - Lu) : T(0);
-                const T Ll = adj_flux<T>(lc, le, lw, ln, ls, fxe, fxw, fyn, fys, ax, ay);
-                nm[c] = in ? (MU[s - 1][0][c] + Ll) : T(0);
-                // gradient (FP64): -w ax [(u_e-u_c)(l_e-l_c) + (u_w-u_c)(l_w-l_c)], likewise in y
-                const double gx = (double)(ue - uc) * (double)(le - lc) + (double)(uw - uc) * (double)(lw - lc);
-                const double gy = (double)(un - uc) * (double)(ln - lc) + (double)(us - uc) * (double)(ls - lc);
-                GX[s - 1][c] += -w * axd * gx;
-                GY[s - 1][c] += -w * ayd * gy;
-            }
-            // adjoint source s_n at the receivers of row r (interior)
-            if (a.R > 0 && rin) {
-                const int kb = a.rec_rowptr[r], ke = a.rec_rowptr[r + 1];
-                for (int k = kb; k < ke; ++k) {
-                    const int off = a.rec_col[k] - cb;
-                    if (off >= 0 && off < C) {
-                        const T sv = (T)a.trace_grad[n * a.R + a.rec_id[k]];
+                    const T hr = lane_from_right(hprev[0]);
 #pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            if (off == c) nm[c] += sv;
+                    for (int c = 0; c < C; ++c) {
+                        FXr[q][c] = hprev[c] + ((c < C - 1) ? hprev[c + 1] : hr);
+                        FYr[q][c] = hprev[c] + bh[pb][c];
                     }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
+                }
+            }
+            // level 0 (time m): row j
+            {
+                const int p0 = pmod(s, 2);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    Ur[0][p0][c] = bu[pb][c];
+                    Dr[0][p0][c] = bd[pb][c];
+                    Lr[0][p0][c] = bl[pb][c];
+                    Mr[0][p0][c] = bm[pb][c];
                 }
             }
 #pragma unroll
-            for (int c = 0; c < C; ++c) nl[c] = (rin && colin[c]) ? (LA[s - 1][1][c] + nm[c]) : T(0);
-            if (s < K) {
+            for (int t = 1; t <= K; ++t) {
+                const int r = j - t;
+                const int pr = pmod(s - t, 2);
+                const int pr1 = pmod(s - t + 1, 2);
+                const int q = pmod(s - t, K);
+                const bool rin = (r >= 1) && (r <= ny - 2);
+                const bool r1in = (r + 1 >= 1) && (r + 1 <= ny - 2);
+                const bool rown = (r >= r0) && (r < r1);
+                const int64_t n = a.n_top - t;  // time of this level's forward state
+                const double w = (n == 0) ? 0.5 : 1.0;
+                // u^{m-t}(r+1) = u^{m-t+1}(r+1) - du^{m-t+1}(r+1)
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    Ur[t][pr1][c] = r1in ? fma_t(-Dr[t - 1][pr1][c], colm[c], Ur[t - 1][pr1][c]) : T(0);
+                // x fluxes and face differences of u^{m-t} and lam^{m-t+1} at row r
+                const T uR = lane_from_right(Ur[t][pr][0]);
+                const T lR = lane_from_right(Lr[t - 1][pr][0]);
+                T Fu[C], Fl[C];
+                double Px[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    D[s][0][c] = D[s][1][c];
-                    D[s][1][c] = nd[c];
-                    LA[s][0][c] = LA[s][1][c];
-                    LA[s][1][c] = LA[s][2][c];
-                    LA[s][2][c] = nl[c];
-                    MU[s][0][c] = MU[s][1][c];
-                    MU[s][1][c] = nm[c];
-                    // newest row of level s+1's u: u^{n-1}(r) = u^n(r) - du^n(r)
-                    W[s][0][c] = W[s][1][c];
-                    W[s][1][c] = W[s][2][c];
-                    W[s][2][c] = (rin && colin[c]) ? (W[s - 1][1][c] - nd[c]) : T(0);
+                    const T du = ((c < C - 1) ? Ur[t][pr][c + 1] : uR) - Ur[t][pr][c];
+                    const T dl = ((c < C - 1) ? Lr[t - 1][pr][c + 1] : lR) - Lr[t - 1][pr][c];
+                    Fu[c] = FXr[q][c] * du;
+                    Fl[c] = FXr[q][c] * dl;
+                    Px[c] = (double)du * (double)dl;
                 }
-            } else if (rown && lane_owned) {
-                const size_t off = (size_t)r * ld + cb;
-                T uo[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) uo[c] = W[s - 1][1][c];
-                astore<T, C>(uout + off, uo);
-                astore<T, C>(dout + off, nd);
-                astore<T, C>(lout + off, nl);
-                astore<T, C>(mout + off, nm);
-            }
-        }
-        // row j - K has all K contributions: add them to the accumulator plane(s)
-        {
-            const int r = j - K;
-            if (r >= r0 && r < r1 && lane_owned) {
-                const size_t off = (size_t)r * ld + cb;
+                const T FuL = lane_from_left(Fu[C - 1]);
+                const T FlL = lane_from_left(Fl[C - 1]);
+                const double PxL = lane_from_left(Px[C - 1]);
+                T nd[C], nm[C], nl[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    if (split) {
-                        a.g1[off + c] += GX[K - 1][c];
-                        a.g2[off + c] += GY[K - 1][c];
+                    const T duy = Ur[t][pr1][c] - Ur[t][pr][c];
+                    const T dly = Lr[t - 1][pr1][c] - Lr[t - 1][pr][c];
+                    const T Gun = FYr[q][c] * duy;
+                    const T Gln = FYr[q][c] * dly;
+                    const double Pyn = (double)duy * (double)dly;
+                    const T Lu = fma_t(ax, Fu[c] - ((c > 0) ? Fu[c - 1] : FuL), ay * (Gun - Gu[t - 1][c]));
+                    const T Ll = fma_t(ax, Fl[c] - ((c > 0) ? Fl[c - 1] : FlL), ay * (Gln - Gl[t - 1][c]));
+                    Gu[t - 1][c] = Gun;
+                    Gl[t - 1][c] = Gln;
+                    const double gx = Px[c] + ((c > 0) ? Px[c - 1] : PxL);
+                    const double gy = Pyn + Py[t - 1][c];
+                    Py[t - 1][c] = Pyn;
+                    GX[q][c] = __builtin_fma(-w * axd, gx, GX[q][c]);
+                    GY[q][c] = __builtin_fma(-w * ayd, gy, GY[q][c]);
+                    if (rin) {
+                        nd[c] = fma_t(-Lu, colm[c], Dr[t - 1][pr][c]);
+                        nm[c] = fma_t(Ll, colm[c], Mr[t - 1][pr][c]);
                     } else {
-                        a.g1[off + c] += GX[K - 1][c] + GY[K - 1][c];
+                        nd[c] = nm[c] = T(0);
                     }
                 }
-            }
+                if (a.R > 0 && rin) {
+                    const int kb = a.rec_rowptr[r], ke = a.rec_rowptr[r + 1];
+                    for (int k = kb; k < ke; ++k) {
+                        const int off = a.rec_col[k] - cb;
+                        if (off >= 0 && off < C) {
+                            const T sv = (T)a.trace_grad[n * a.R + a.rec_id[k]];
 #pragma unroll
-            for (int s = K - 1; s > 0; --s)
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    GX[s][c] = GX[s - 1][c];
-                    GY[s][c] = GY[s - 1][c];
+                            for (int c = 0; c < C; ++c)
+                                if (off == c) nm[c] += sv;
+                        }
+                    }
                 }
 #pragma unroll
-            for (int c = 0; c < C; ++c) GX[0][c] = GY[0][c] = 0.0;
+                for (int c = 0; c < C; ++c) nl[c] = rin ? fma_t(nm[c], colm[c], Lr[t - 1][pr][c]) : T(0);
+                if (t < K) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        Dr[t][pr][c] = nd[c];
+                        Lr[t][pr][c] = nl[c];
+                        Mr[t][pr][c] = nm[c];
+                    }
+                } else if (rown && lane_owned) {
+                    const size_t off = (size_t)(ptrdiff_t)r * ld + (size_t)(ptrdiff_t)cb;
+                    T uo[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) uo[c] = Ur[t][pr][c];
+                    store_pack<T, C>(uout + off, uo);
+                    store_pack<T, C>(dout + off, nd);
+                    store_pack<T, C>(lout + off, nl);
+                    store_pack<T, C>(mout + off, nm);
+                }
+            }
+            // row j-K has all K contributions (ring index (j-K-jb) mod K = s mod K)
+            {
+                const int qd = pmod(s, K);
+                const int r = j - K;
+                if (r >= r0 && r < r1 && lane_owned) {
+                    const size_t off = (size_t)(ptrdiff_t)r * ld + (size_t)(ptrdiff_t)cb;
+                    double o1[C], o2[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        if (split) {
+                            o1[c] = g1old[c] + GX[qd][c];
+                            o2[c] = g2old[c] + GY[qd][c];
+                        } else {
+                            o1[c] = g1old[c] + (GX[qd][c] + GY[qd][c]);
+                        }
+                    }
+                    store_pack<double, C>(a.g1 + off, o1);
+                    if (split) store_pack<double, C>(a.g2 + off, o2);
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) GX[qd][c] = GY[qd][c] = 0.0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
 
-template <typename T, int K>
-static hipError_t adj_launch_k(const AdjArgs& a, int grid, hipStream_t s)
+template <typename T, int K, int C>
+static hipError_t adj_launch_kc(const AdjArgs& a, int grid, hipStream_t s)
 {
     if (a.face)
-        hipLaunchKernelGGL((k_adjoint<T, K, 1>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint<T, K, C, 1>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_adjoint<T, K, 0>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint<T, K, C, 0>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_adjoint_block(const AdjArgs& a, int K, int grid, hipStream_t s)
+template <typename T, int C>
+static hipError_t adj_launch_c(const AdjArgs& a, int K, int grid, hipStream_t s)
 {
     switch (K) {
-    case 1: return adj_launch_k<T, 1>(a, grid, s);
-    case 2: return adj_launch_k<T, 2>(a, grid, s);
-    case 3: return adj_launch_k<T, 3>(a, grid, s);
-    case 4: return adj_launch_k<T, 4>(a, grid, s);
+    case 1: return adj_launch_kc<T, 1, C>(a, grid, s);
+    case 2: return adj_launch_kc<T, 2, C>(a, grid, s);
+    case 3: return adj_launch_kc<T, 3, C>(a, grid, s);
+    case 4: return adj_launch_kc<T, 4, C>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_adjoint_block<float>(const AdjArgs&, int, int, hipStream_t);
-template hipError_t launch_adjoint_block<double>(const AdjArgs&, int, int, hipStream_t);
+
+template <>
+hipError_t launch_adjoint_block<float>(const AdjArgs& a, int K, int C, int grid, hipStream_t s)
+{
+    if (C == 2) return adj_launch_c<float, 2>(a, K, grid, s);
+    if (C == 4) return adj_launch_c<float, 4>(a, K, grid, s);
+    return hipErrorInvalidValue;
+}
+template <>
+hipError_t launch_adjoint_block<double>(const AdjArgs& a, int K, int C, int grid, hipStream_t s)
+{
+    if (C == 1) return adj_launch_c<double, 1>(a, K, grid, s);
+    if (C == 2) return adj_launch_c<double, 2>(a, K, grid, s);
+    return hipErrorInvalidValue;
+}
 
 // lam^N = mu^N = s_N at the receivers (planes already zero).
 template <typename T>

@@ -26,7 +26,13 @@ namespace {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-inline int cols_per_lane(int dtype) { return dtype == FDW_F32 ? 4 : 2; }
+inline int default_cols_per_lane(int dtype) { return dtype == FDW_F32 ? 2 : 2; }
+// every plane carries zero rows above and below the grid (streamed rows may run past it)
+inline size_t plane_alloc(int ld, int ny, size_t es)
+{
+    return (size_t)ld * (size_t)(kPadRowsTop + ny + kPadRowsBottom) * es;
+}
+inline void* plane_origin(void* base, int ld, size_t es) { return (char*)base + (size_t)kPadRowsTop * ld * es; }
 inline size_t elem_size(int dtype) { return dtype == FDW_F32 ? 4 : 8; }
 inline int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }
 constexpr int kMinSegRows = 16;
@@ -77,6 +83,8 @@ struct fdw_ctx {
     int* barrier = nullptr;
     double* scal = nullptr;  // small device scalars (energies read back by fdw_energy)
     int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0, timing = 0;
+    int C = 4;  // columns per lane of the streaming kernels
+    int adjK = 2, adjC = 2;  // time block and columns per lane of the reverse sweep
     std::vector<hipEvent_t> ev_pool;  // instrumentation: start/end pairs of stencil launches
     size_t ev_used = 0;
     int S_eff = 0;
@@ -117,8 +125,10 @@ bool problem_ok(const fdw_problem& p, std::string* why, int64_t* N_out)
     return true;
 }
 
-int max_strips(int nx, int C)
+int max_strips(int nx)
 {
+    // narrowest strip: 2 columns per lane, 8-step time block
+    const int C = 2;
     const int Hx = ((kMaxTimeBlock + C - 1) / C) * C;
     const int Wv = kWaveSize * C - 2 * Hx;
     return (nx + Wv - 1) / Wv;
@@ -127,9 +137,8 @@ int max_strips(int nx, int C)
 size_t member_bytes(const fdw_problem& p)
 {
     const int ld = pitch_of(p.nx);
-    const size_t plane = align_up((size_t)ld * p.ny * elem_size(p.dtype), kAlign);
-    const int C = cols_per_lane(p.dtype);
-    const size_t maxw = (size_t)max_strips(p.nx, C) * (size_t)((p.ny + kMinSegRows - 1) / kMinSegRows);
+    const size_t plane = align_up(plane_alloc(ld, p.ny, elem_size(p.dtype)), kAlign);
+    const size_t maxw = (size_t)max_strips(p.nx) * (size_t)((p.ny + kMinSegRows - 1) / kMinSegRows);
     size_t b = 8 * plane;                                          // u[2], d[2], h, hy, u0, u1
     b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);        // rec_ij
     b += align_up(sizeof(int) * (size_t)(p.ny + 1), kAlign);       // rowptr
@@ -150,7 +159,7 @@ size_t header_bytes(int count)
 
 void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int K)
 {
-    const int C = cols_per_lane(c->dtype);
+    const int C = c->C;
     const int Hx = ((K + C - 1) / C) * C;
     const int Wv = kWaveSize * C - 2 * Hx;
     md.seg_rows = S;
@@ -173,8 +182,7 @@ int choose_S(const fdw_ctx* c)
     // of at least 64 rows so that the 2K-row pipeline fill stays a small fraction.
     int best = 64;
     for (const HostMember& hm : c->m) {
-        const int C = cols_per_lane(c->dtype);
-        const int strips = max_strips(hm.nx, C);
+        const int strips = max_strips(hm.nx);
         int64_t want = ((int64_t)hm.ny * strips + 2047) / 2048;
         int S = (int)std::max<int64_t>(64, want);
         S = (S + 7) / 8 * 8;
@@ -261,7 +269,7 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
             a.nmembers = 1;
             a.block_offset = c->tab[i].block_base;
             a.total_blocks = c->tab[i].blocks;
-            HIPCHK(c, launch_step<T>(a, K, c->m[i].face, a.total_blocks, s));
+            HIPCHK(c, launch_step<T>(a, K, c->C, c->m[i].face, a.total_blocks, s));
         }
         return FDW_OK;
     }
@@ -274,7 +282,7 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
         }
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
     }
-    HIPCHK(c, launch_step<T>(a, K, face_mode, total, s));
+    HIPCHK(c, launch_step<T>(a, K, c->C, face_mode, total, s));
     if (timed) {
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
         c->ev_used += 2;
@@ -340,7 +348,7 @@ int run_persistent(fdw_ctx* c, int64_t steps)
     const int64_t tail = steps - phases * K;
     int total = 0;
     for (const MemberDev& md : c->tab) total += md.blocks;
-    int grid = std::min(total, persistent_max_blocks<T>(K, face_mode));
+    int grid = std::min(total, persistent_max_blocks<T>(K, c->C, face_mode));
     if (grid < 1) return fail(c, FDW_EHIP, "persistent launch: no resident blocks");
     if (phases > 0) {
         HIPCHK(c, launch_fill_bytes(c->barrier, 16 * sizeof(int), c->stream));
@@ -355,7 +363,7 @@ int run_persistent(fdw_ctx* c, int64_t steps)
         a.want_trace = 0;
         a.ctx_step = c->ctx_step;
         if (phases > INT32_MAX) return fail(c, FDW_EINVAL, "too many steps for one persistent launch");
-        HIPCHK(c, launch_step_persistent<T>(a, K, face_mode, (int)phases, grid, c->barrier, c->stream));
+        HIPCHK(c, launch_step_persistent<T>(a, K, c->C, face_mode, (int)phases, grid, c->barrier, c->stream));
         c->ctx_step += phases * K;
         c->launches += phases;
         for (HostMember& hm : c->m) {
@@ -502,6 +510,9 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
     fdw_ctx* c = new fdw_ctx();
     c->count = count;
     c->dtype = problems[0].dtype;
+    c->C = default_cols_per_lane(c->dtype);
+    c->adjC = (c->dtype == FDW_F64) ? 1 : 2;
+    c->adjK = 2;
     c->stream = (hipStream_t)hip_stream;
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
@@ -532,19 +543,20 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
         hm.dx = (p.x1 - p.x0) / (p.nx - 1);
         hm.dy = (p.y1 - p.y0) / (p.ny - 1);
         hm.tau = p.tau;
-        hm.plane_bytes = align_up((size_t)hm.ld * p.ny * elem_size(c->dtype), kAlign);
-        for (int k = 0; k < 2; ++k) hm.u[k] = take(hm.plane_bytes);
-        for (int k = 0; k < 2; ++k) hm.d[k] = take(hm.plane_bytes);
-        hm.h = take(hm.plane_bytes);
-        hm.hy = take(hm.plane_bytes);
-        hm.u0 = take(hm.plane_bytes);
-        hm.u1 = take(hm.plane_bytes);
+        const size_t es = elem_size(c->dtype);
+        hm.plane_bytes = align_up(plane_alloc(hm.ld, p.ny, es), kAlign);
+        auto plane = [&]() { return plane_origin(take(hm.plane_bytes), hm.ld, es); };
+        for (int k = 0; k < 2; ++k) hm.u[k] = plane();
+        for (int k = 0; k < 2; ++k) hm.d[k] = plane();
+        hm.h = plane();
+        hm.hy = plane();
+        hm.u0 = plane();
+        hm.u1 = plane();
         hm.rec_ij = (int*)take(sizeof(int) * 2 * kMaxReceivers);
         hm.rowptr = (int*)take(sizeof(int) * (size_t)(p.ny + 1));
         hm.rcol = (int*)take(sizeof(int) * kMaxReceivers);
         hm.rid = (int*)take(sizeof(int) * kMaxReceivers);
-        const int C = cols_per_lane(c->dtype);
-        hm.epart_stride = max_strips(p.nx, C) * ((p.ny + kMinSegRows - 1) / kMinSegRows);
+        hm.epart_stride = max_strips(p.nx) * ((p.ny + kMinSegRows - 1) / kMinSegRows);
         hm.epart = (double*)take(sizeof(double) * kMaxTimeBlock * (size_t)hm.epart_stride);
 
         MemberDev& md = c->tab[i];
@@ -796,7 +808,9 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
     if (!c) return FDW_EINVAL;
     switch (key) {
     case FDW_CFG_TIME_BLOCK:
-        if (v < 0 || v > kMaxTimeBlock) return fail(c, FDW_EINVAL, "time block must be 0..8");
+        if (v < 0 || v > kMaxTimeBlock || (c->dtype == FDW_F64 && v > 4) || (c->C == 4 && v > 6))
+            return fail(c, FDW_EINVAL, "time block must be 0..8 (float, 2 columns per lane), 0..6 (float, 4 columns) "
+                                       "or 0..4 (double)");
         c->K_cfg = (int)v;
         break;
     case FDW_CFG_SEGMENT_ROWS:
@@ -815,6 +829,24 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
     case FDW_CFG_TIMING:
         if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "timing must be 0 or 1");
         c->timing = (int)v;
+        break;
+    case FDW_CFG_LANE_COLUMNS:
+        if (v == 0) v = default_cols_per_lane(c->dtype);
+        if (!(v == 2 || (v == 4 && c->dtype == FDW_F32)))
+            return fail(c, FDW_EINVAL, "lane columns must be 2 or 4 (float) / 2 (double)");
+        if (v == 4 && c->K_cfg > 6) return fail(c, FDW_EINVAL, "4 columns per lane supports time blocks up to 6");
+        c->C = (int)v;
+        break;
+    case FDW_CFG_ADJ_TIME_BLOCK:
+        if (v == 0) v = 2;
+        if (v < 1 || v > 4) return fail(c, FDW_EINVAL, "adjoint time block must be 1..4");
+        c->adjK = (int)v;
+        break;
+    case FDW_CFG_ADJ_LANE_COLUMNS:
+        if (v == 0) v = (c->dtype == FDW_F64) ? 1 : 2;
+        if (!(v == 2 || (v == 4 && c->dtype == FDW_F32) || (v == 1 && c->dtype == FDW_F64)))
+            return fail(c, FDW_EINVAL, "adjoint lane columns must be 2 or 4 (float) / 1 or 2 (double)");
+        c->adjC = (int)v;
         break;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
@@ -848,6 +880,9 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
     case FDW_CFG_USE_GRAPH: return c->use_graph;
     case FDW_CFG_BATCH_MODE: return c->batch_mode;
     case FDW_CFG_TIMING: return c->timing;
+    case FDW_CFG_LANE_COLUMNS: return c->C;
+    case FDW_CFG_ADJ_TIME_BLOCK: return c->adjK;
+    case FDW_CFG_ADJ_LANE_COLUMNS: return c->adjC;
     default: return -1;
     }
 }
@@ -855,11 +890,11 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
 }  // extern "C"
 
 // =============================================================================================
-// Adjoint driver (a8, a9)
+// Adjoint driver: forward replay with checkpoints, reverse sweep
 // =============================================================================================
 namespace {
 
-int adjoint_K(const fdw_ctx* c) { return c->dtype == FDW_F32 ? 2 : 2; }
+int adjoint_K(const fdw_ctx* c) { return c->adjK; }
 
 struct AdjLayout {
     size_t plane = 0, plane64 = 0;
@@ -870,7 +905,7 @@ struct AdjLayout {
 AdjLayout adj_layout(const fdw_ctx* c, const HostMember& hm, int ck)
 {
     AdjLayout L;
-    L.plane = align_up((size_t)hm.ld * hm.ny * elem_size(c->dtype), kAlign);
+    L.plane = align_up(plane_alloc(hm.ld, hm.ny, elem_size(c->dtype)), kAlign);
     L.plane64 = align_up((size_t)hm.ld * hm.ny * sizeof(double), kAlign);
     L.nck = (hm.N >= 1 && ck >= 1) ? (hm.N - 1) / ck : 0;  // checkpoints at ck, 2ck, ... < N
     size_t b = align_up(sizeof(MemberDev), kAlign);
@@ -886,7 +921,7 @@ AdjLayout adj_layout(const fdw_ctx* c, const HostMember& hm, int ck)
 
 void adj_decompose(const fdw_ctx* c, const HostMember& hm, int K, int S, AdjArgs& a)
 {
-    const int C = cols_per_lane(c->dtype);
+    const int C = c->adjC;
     const int Hx = ((K + C - 1) / C) * C;
     const int Wv = kWaveSize * C - 2 * Hx;
     a.seg_rows = S;
@@ -914,16 +949,19 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     void* FD[2];
     void* LA[2];
     void* MU[2];
-    for (int k = 0; k < 2; ++k) FU[k] = take(L.plane);
-    for (int k = 0; k < 2; ++k) FD[k] = take(L.plane);
-    for (int k = 0; k < 2; ++k) LA[k] = take(L.plane);
-    for (int k = 0; k < 2; ++k) MU[k] = take(L.plane);
+    const size_t es = elem_size(c->dtype);
+    void* planes_begin = w + off;
+    auto plane = [&]() { return plane_origin(take(L.plane), hm.ld, es); };
+    for (int k = 0; k < 2; ++k) FU[k] = plane();
+    for (int k = 0; k < 2; ++k) FD[k] = plane();
+    for (int k = 0; k < 2; ++k) LA[k] = plane();
+    for (int k = 0; k < 2; ++k) MU[k] = plane();
     double* G1 = (double*)take(L.plane64);
     double* G2 = (double*)take(L.plane64);
     std::vector<void*> CU(L.nck), CD(L.nck);
     for (int64_t k = 0; k < L.nck; ++k) {
-        CU[k] = take(L.plane);
-        CD[k] = take(L.plane);
+        CU[k] = plane();
+        CD[k] = plane();
     }
     int* rec = (int*)take(sizeof(int) * 2 * kMaxReceivers);
     int* rowptr = (int*)take(sizeof(int) * (size_t)(hm.ny + 1));
@@ -933,7 +971,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     hipStream_t s = c->stream;
 
     // zero the state planes (boundary ring and padding must be 0) and the accumulators
-    HIPCHK(c, launch_fill_bytes(FU[0], 8 * L.plane + 2 * L.plane64, s));
+    HIPCHK(c, launch_fill_bytes(planes_begin, 8 * L.plane + 2 * L.plane64, s));
     if (R > 0) {
         HIPCHK(c, hipMemcpyAsync(rec, recv_ij, sizeof(int) * 2 * (size_t)R, hipMemcpyDeviceToDevice, s));
         HIPCHK(c, launch_receivers_csr(rec, R, hm.nx, hm.ny, rowptr, rcol, rid, status, s));
@@ -967,8 +1005,10 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     int pushedK = -1;
     auto store_ckpt = [&](int64_t step) -> int {
         const int64_t k = step / ck - 1;
-        HIPCHK(c, hipMemcpyAsync(CU[k], FU[cur], L.plane, hipMemcpyDeviceToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(CD[k], FD[cur], L.plane, hipMemcpyDeviceToDevice, s));
+        const size_t pad = (size_t)kPadRowsTop * hm.ld * es;
+        const size_t bytes = plane_alloc(hm.ld, hm.ny, es);
+        HIPCHK(c, hipMemcpyAsync((char*)CU[k] - pad, (char*)FU[cur] - pad, bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync((char*)CD[k] - pad, (char*)FD[cur] - pad, bytes, hipMemcpyDeviceToDevice, s));
         return FDW_OK;
     };
     if (n % ck == 0 && n < N) {
@@ -994,7 +1034,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
         a.want_energy = 0;
         a.want_trace = 0;
         a.ctx_step = 0;
-        HIPCHK(c, launch_step<T>(a, Kb, hm.face, rep.blocks, s));
+        HIPCHK(c, launch_step<T>(a, Kb, c->C, hm.face, rep.blocks, s));
         cur ^= 1;
         n += Kb;
         if (n % ck == 0 && n < N) {
@@ -1053,7 +1093,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
         A.mout = MU[lcur ^ 1];
         A.n_top = mtop;
         const int grid = (A.waves + kWavesPerBlock - 1) / kWavesPerBlock;
-        HIPCHK(c, launch_adjoint_block<T>(A, Kb, grid, s));
+        HIPCHK(c, launch_adjoint_block<T>(A, Kb, c->adjC, grid, s));
         fu_in = FU[outk];
         fd_in = FD[outk];
         fcur = outk;
@@ -1115,7 +1155,7 @@ std::string tune_key(const fdw_ctx* c)
     return os.str();
 }
 
-bool cache_lookup(const std::string& key, int* K, int* S)
+bool cache_lookup(const std::string& key, int* K, int* S, int* C)
 {
     const char* path = std::getenv("FDW_AUTOTUNE_CACHE");
     if (!path || !*path) return false;
@@ -1127,22 +1167,23 @@ bool cache_lookup(const std::string& key, int* K, int* S)
         if (bar == std::string::npos) continue;
         if (line.substr(0, bar) != key) continue;
         std::istringstream is(line.substr(bar + 1));
-        int k = 0, sr = 0;
-        if (is >> k >> sr) {
+        int k = 0, sr = 0, cc = 0;
+        if (is >> k >> sr >> cc) {
             *K = k;
             *S = sr;
+            *C = cc;
             found = true;  // last entry wins
         }
     }
     return found;
 }
 
-void cache_store(const std::string& key, int K, int S)
+void cache_store(const std::string& key, int K, int S, int C)
 {
     const char* path = std::getenv("FDW_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     std::ofstream f(path, std::ios::app);
-    f << key << "|" << K << " " << S << "\n";
+    f << key << "|" << K << " " << S << " " << C << "\n";
 }
 
 }  // namespace
@@ -1155,8 +1196,8 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         if (hm.n != 0) return fail(c, FDW_ESTATE, "autotune runs from step 0 (call fdw_reset first)");
     }
     const std::string key = tune_key(c);
-    int bestK = 0, bestS = 0;
-    if (!cache_lookup(key, &bestK, &bestS)) {
+    int bestK = 0, bestS = 0, bestC_out = c->C;
+    if (!cache_lookup(key, &bestK, &bestS, &bestC_out)) {
         int maxny = 0;
         int64_t points = 0;
         for (const HostMember& hm : c->m) {
@@ -1165,25 +1206,32 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         }
         int nsteps = steps > 0 ? steps : (int)std::max<int64_t>(16, std::min<int64_t>(256, (int64_t)4e9 / std::max<int64_t>(points, 1)));
         nsteps = std::max(nsteps, 2 * kMaxTimeBlock);
-        const int Ks32[] = {1, 2, 3, 4, 5, 6, 8};
-        const int Ks64[] = {1, 2, 3, 4};
-        const int* Ks = c->dtype == FDW_F32 ? Ks32 : Ks64;
-        const int nK = c->dtype == FDW_F32 ? 7 : 4;
-        const int Ss[] = {32, 64, 128, 256, 512, 1024};
-        const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode;
+        // candidates: (columns per lane, time block) pairs the kernels support, x segment rows
+        std::vector<std::pair<int, int>> CK;
+        if (c->dtype == FDW_F32) {
+            for (int K = 1; K <= 8; ++K) CK.push_back({2, K});
+            for (int K = 1; K <= 6; ++K) CK.push_back({4, K});
+        } else {
+            for (int K = 1; K <= 4; ++K) CK.push_back({2, K});
+        }
+        const int Ss[] = {32, 64, 128, 256, 512};
+        const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode, saveC = c->C;
         c->use_graph = 0;
         c->batch_mode = 0;
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
         float best = 1e30f;
-        for (int ki = 0; ki < nK; ++ki) {
+        int bestC = c->C;
+        for (const auto& ck : CK) {
             for (int S : Ss) {
                 if (S > 2 * maxny && S != 32) continue;
-                c->K_cfg = Ks[ki];
+                const int Kc = ck.second;
+                c->C = ck.first;
+                c->K_cfg = Kc;
                 c->S_cfg = S;
                 c->S_eff = S;
-                int rc = layout_for_K(c, Ks[ki], S);
+                int rc = layout_for_K(c, Kc, S);
                 if (rc) return rc;
                 float med = 0.f;
                 std::vector<float> ts;
@@ -1193,7 +1241,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
                         c->m[i].cur = 0;
                         sync_member_dev(c, i);
                     }
-                    rc = layout_for_K(c, Ks[ki], S);
+                    rc = layout_for_K(c, Kc, S);
                     if (rc) return rc;
                     rc = fdw_step_n(c, 1, nullptr);  // start step, outside the timed region
                     if (rc) return rc;
@@ -1208,11 +1256,12 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
                 }
                 std::sort(ts.begin(), ts.end());
                 med = ts[1];
-                // prefer the smaller time block unless the larger one is at least 2% faster
-                if (med < best * 0.98f || (med < best && Ks[ki] == bestK)) {
+                // candidates come in increasing time block; a later one must be 2% faster
+                if (med < best * 0.98f || (med < best && Kc == bestK)) {
                     best = med;
-                    bestK = Ks[ki];
+                    bestK = Kc;
                     bestS = S;
+                    bestC = ck.first;
                 }
             }
         }
@@ -1222,8 +1271,11 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         c->batch_mode = saveB;
         (void)saveK;
         (void)saveS;
-        cache_store(key, bestK, bestS);
+        (void)saveC;
+        bestC_out = bestC;
+        cache_store(key, bestK, bestS, bestC);
     }
+    c->C = bestC_out;
     c->K_cfg = bestK;
     c->S_cfg = bestS;
     c->S_eff = bestS;
@@ -1238,6 +1290,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
     if (best_out) {
         best_out[0] = bestK;
         best_out[1] = bestS;
+        best_out[2] = c->C;
     }
     return FDW_OK;
 }

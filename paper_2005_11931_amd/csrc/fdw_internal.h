@@ -16,6 +16,8 @@ constexpr int kWaveSize = 64;         // CDNA wavefront
 constexpr int kWavesPerBlock = 4;     // independent streaming waves per workgroup
 constexpr int kMaxReceivers = 16384;  // per member
 constexpr int kRedBlocks = 1024;      // blocks of the generic two-stage reductions
+constexpr int kPadRowsTop = 0;        // rows reserved above / below each plane (none needed: the
+constexpr int kPadRowsBottom = 0;     // streaming kernel's buffer loads return 0 outside the grid)
 
 // Static description of one member, resident in device memory (the member table).
 struct MemberDev {
@@ -61,13 +63,14 @@ struct StepArgs {
 
 // ---- launchers (fdw_kernels.hip) ---------------------------------------------------------
 // All return hipError_t of the launch.
+// C = columns per lane (float: 2 or 4; double: 2)
 template <typename T>
-hipError_t launch_step(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s);
 template <typename T>
-hipError_t launch_step_persistent(const StepArgs& a, int K, int face_mode, int phases, int grid, int* barrier,
+hipError_t launch_step_persistent(const StepArgs& a, int K, int C, int face_mode, int phases, int grid, int* barrier,
                                   hipStream_t s);
 template <typename T>
-int persistent_max_blocks(int K, int face_mode);
+int persistent_max_blocks(int K, int C, int face_mode);
 
 template <typename T>
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
@@ -120,9 +123,7 @@ struct AdjArgs {
     int strips, segs, seg_rows, waves;
 };
 template <typename T>
-hipError_t launch_adjoint_block(const AdjArgs& a, int K, int grid, hipStream_t s);
-template <typename T>
-hipError_t launch_adjoint_start_term(const AdjArgs& a, const void* u0, hipStream_t s);
+hipError_t launch_adjoint_block(const AdjArgs& a, int K, int C, int grid, hipStream_t s);
 template <typename T>
 hipError_t launch_adjoint_seed(const AdjArgs& a, int64_t N, hipStream_t s);
 hipError_t launch_grad_out(const double* g, int ld, int nx, int ny, double* out, hipStream_t s);

@@ -21,476 +21,67 @@
 // Energy (discrete CL-01 of Section 2): E^{n+1/2} = (dx dy / tau^2) sum (du^{n+1})^2 - u^{n+1} L(u^n),
 // accumulated in FP64 per wave, reduced in a fixed order.
 #include "fdw_internal.h"
+#include "fdw_stream.h"
 
 #include <hip/hip_runtime.h>
 
 namespace fdw {
 
-// ------------------------------------------------------------------------------------------
-// Lane exchange across the whole wave (DPP wave shift by one lane; lanes with no source get 0)
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int lane_from_left_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // lane l <- lane l-1
-}
-__device__ __forceinline__ int lane_from_right_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // lane l <- lane l+1
-}
-__device__ __forceinline__ float lane_from_left(float v)
-{
-    return __builtin_bit_cast(float, lane_from_left_i(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ float lane_from_right(float v)
-{
-    return __builtin_bit_cast(float, lane_from_right_i(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double lane_from_left(double v)
-{
-    long long b = __builtin_bit_cast(long long, v);
-    int lo = lane_from_left_i((int)(b & 0xffffffffLL));
-    int hi = lane_from_left_i((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double lane_from_right(double v)
-{
-    long long b = __builtin_bit_cast(long long, v);
-    int lo = lane_from_right_i((int)(b & 0xffffffffLL));
-    int hi = lane_from_right_i((int)(b >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
+// stencil launchers, one per instantiation unit (fdw_step_*.hip)
+hipError_t launch_step_f32c4(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
+hipError_t launch_step_f32c2(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
+hipError_t launch_step_f64c2(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
+hipError_t launch_persistent_f32c4(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                   hipStream_t s);
+hipError_t launch_persistent_f32c2(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                   hipStream_t s);
+hipError_t launch_persistent_f64c2(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                   hipStream_t s);
+int persistent_max_f32c4(int K, int face_mode);
+int persistent_max_f32c2(int K, int face_mode);
+int persistent_max_f64c2(int K, int face_mode);
 
-// ------------------------------------------------------------------------------------------
-// The point update, shared by every kernel that advances the state.
-//   f* are face sums (2x the face coefficient: h_c + h_neighbour), ax = tau^2/(2 dx^2).
-// Opposite faces are added as commutative pairs so that mirror-symmetric data stay
-// mirror-symmetric bit for bit.  The file is compiled without contraction; the one fused
-// multiply-add is explicit.
-// ------------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T flux_L(T uc, T ue, T uw, T un, T us, T fxe, T fxw, T fyn, T fys, T ax, T ay)
+template <>
+hipError_t launch_step<float>(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s)
 {
-    T pe = fxe * (ue - uc);
-    T pw = fxw * (uw - uc);
-    T pn = fyn * (un - uc);
-    T ps = fys * (us - uc);
-    T sx = pe + pw;
-    T sy = pn + ps;
-    return __builtin_fma(ax, sx, ay * sy);
+    if (C == 4) return launch_step_f32c4(a, K, face_mode, grid, s);
+    if (C == 2) return launch_step_f32c2(a, K, face_mode, grid, s);
+    return hipErrorInvalidValue;
 }
 template <>
-__device__ __forceinline__ float flux_L<float>(float uc, float ue, float uw, float un, float us, float fxe, float fxw,
-                                               float fyn, float fys, float ax, float ay)
+hipError_t launch_step<double>(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s)
 {
-    float pe = fxe * (ue - uc);
-    float pw = fxw * (uw - uc);
-    float pn = fyn * (un - uc);
-    float ps = fys * (us - uc);
-    float sx = pe + pw;
-    float sy = pn + ps;
-    return __builtin_fmaf(ax, sx, ay * sy);
+    if (C == 2) return launch_step_f64c2(a, K, face_mode, grid, s);
+    return hipErrorInvalidValue;
 }
-
-template <typename T, int C>
-struct alignas(sizeof(T) * C) Pack {
-    T v[C];
-};
-
-template <typename T, int C>
-__device__ __forceinline__ void load_pack(const T* __restrict__ p, T (&out)[C])
-{
-    Pack<T, C> q = *reinterpret_cast<const Pack<T, C>*>(p);
-#pragma unroll
-    for (int c = 0; c < C; ++c) out[c] = q.v[c];
-}
-template <typename T, int C>
-__device__ __forceinline__ void store_pack(T* __restrict__ p, const T (&in)[C])
-{
-    Pack<T, C> q;
-#pragma unroll
-    for (int c = 0; c < C; ++c) q.v[c] = in[c];
-    *reinterpret_cast<Pack<T, C>*>(p) = q;
-}
-
-template <typename T>
-struct Lanes;  // columns per lane: one 16-byte vector
 template <>
-struct Lanes<float> {
-    static constexpr int C = 4;
-};
+hipError_t launch_step_persistent<float>(const StepArgs& a, int K, int C, int face_mode, int phases, int grid, int* bar,
+                                         hipStream_t s)
+{
+    if (C == 4) return launch_persistent_f32c4(a, K, face_mode, phases, grid, bar, s);
+    if (C == 2) return launch_persistent_f32c2(a, K, face_mode, phases, grid, bar, s);
+    return hipErrorInvalidValue;
+}
 template <>
-struct Lanes<double> {
-    static constexpr int C = 2;
-};
-
-__device__ __forceinline__ int xcd_remap(int b, int nb)
+hipError_t launch_step_persistent<double>(const StepArgs& a, int K, int C, int face_mode, int phases, int grid,
+                                          int* bar, hipStream_t s)
 {
-    // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give each
-    // XCD a contiguous range of logical blocks so that neighbouring strips share an L2.
-    int xcd = b & 7, per = nb >> 3, rem = nb & 7;
-    return xcd * per + min(xcd, rem) + (b >> 3);
+    if (C == 2) return launch_persistent_f64c2(a, K, face_mode, phases, grid, bar, s);
+    return hipErrorInvalidValue;
 }
-
-__device__ __forceinline__ double wave_sum(double v)
+template <>
+int persistent_max_blocks<float>(int K, int C, int face_mode)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    if (C == 4) return persistent_max_f32c4(K, face_mode);
+    if (C == 2) return persistent_max_f32c2(K, face_mode);
+    return 0;
 }
-
-// ------------------------------------------------------------------------------------------
-// One streaming work item: member M, strip, segment; K time levels.
-// ------------------------------------------------------------------------------------------
-template <typename T, int K, int FACE>
-__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step, int want_energy,
-                                           int want_trace)
+template <>
+int persistent_max_blocks<double>(int K, int C, int face_mode)
 {
-    constexpr int C = Lanes<T>::C;
-    constexpr int Hx = ((K + C - 1) / C) * C;  // halo columns on each side (multiple of C)
-    constexpr int Wv = kWaveSize * C - 2 * Hx;  // owned columns per strip
-    const int lane = threadIdx.x & 63;
-
-    const int nx = M.nx, ny = M.ny, ld = M.ld;
-    const int strip = wave % M.strips;
-    const int seg = wave / M.strips;
-    const int ws = strip * Wv - Hx;
-    const int cb = ws + lane * C;
-    const bool lane_live = (cb >= 0) && (cb < ld);
-    const bool lane_owned = lane_live && (lane * C >= Hx) && (lane * C < Hx + Wv);
-    bool colin[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) colin[c] = (cb + c >= 1) && (cb + c <= nx - 2);
-
-    const int r0 = seg * M.seg_rows;
-    const int r1 = min(r0 + M.seg_rows, ny);
-    const int cur = M.cur0 ^ parity;
-    const T* __restrict__ uin = (const T*)M.u[cur];
-    const T* __restrict__ din = (const T*)M.d[cur];
-    T* __restrict__ uout = (T*)M.u[cur ^ 1];
-    T* __restrict__ dout = (T*)M.d[cur ^ 1];
-    const T* __restrict__ hp = (const T*)M.h;
-    const T* __restrict__ hyp = (const T*)M.hy;
-    const T ax = (T)M.ax, ay = (T)M.ay;
-    const int64_t n0 = ctx_step + M.n_offset;
-
-    // Level rings: U[t] holds level t at rows (r-1, r, r+1) for the row r that level t+1
-    // computes next; D[t] holds level t's increment at rows (r, r+1).
-    T U[K][3][C];
-    T D[K][2][C];
-    // Coefficient rings.  Nodal: rows j-K-1 .. j with one halo column per side.
-    // Face: FX rows j-K .. j with the left halo column, FY rows j-K-1 .. j.
-    constexpr int HR = FACE ? 1 : (K + 2);
-    constexpr int XR = FACE ? (K + 1) : 1;
-    constexpr int YR = FACE ? (K + 2) : 1;
-    T Hn[HR][C + 2];
-    T FX[XR][C + 1];
-    T FY[YR][C];
-#pragma unroll
-    for (int t = 0; t < K; ++t)
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            U[t][0][c] = U[t][1][c] = U[t][2][c] = T(0);
-            D[t][0][c] = D[t][1][c] = T(0);
-        }
-#pragma unroll
-    for (int q = 0; q < HR; ++q)
-#pragma unroll
-        for (int c = 0; c < C + 2; ++c) Hn[q][c] = T(0);
-#pragma unroll
-    for (int q = 0; q < XR; ++q)
-#pragma unroll
-        for (int c = 0; c < C + 1; ++c) FX[q][c] = T(0);
-#pragma unroll
-    for (int q = 0; q < YR; ++q)
-#pragma unroll
-        for (int c = 0; c < C; ++c) FY[q][c] = T(0);
-
-    double acc[K];
-#pragma unroll
-    for (int t = 0; t < K; ++t) acc[t] = 0.0;
-
-    for (int j = r0 - K; j < r1 + K; ++j) {
-        // ---- level 0: row j of the input state and of the coefficient
-        T nu0[C], nd0[C], nh0[C], ny0[C];
-        const bool rl = lane_live && (j >= 0) && (j < ny);
-        if (rl) {
-            const size_t off = (size_t)j * ld + cb;
-            load_pack<T, C>(uin + off, nu0);
-            load_pack<T, C>(din + off, nd0);
-            load_pack<T, C>(hp + off, nh0);
-            if (FACE) load_pack<T, C>(hyp + off, ny0);
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c) nu0[c] = nd0[c] = nh0[c] = ny0[c] = T(0);
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            U[0][0][c] = U[0][1][c];
-            U[0][1][c] = U[0][2][c];
-            U[0][2][c] = nu0[c];
-            D[0][0][c] = D[0][1][c];
-            D[0][1][c] = nd0[c];
-        }
-        if (FACE) {
-#pragma unroll
-            for (int q = 0; q < XR - 1; ++q)
-#pragma unroll
-                for (int c = 0; c < C + 1; ++c) FX[q][c] = FX[q + 1][c];
-            FX[XR - 1][0] = lane_from_left(nh0[C - 1]);
-#pragma unroll
-            for (int c = 0; c < C; ++c) FX[XR - 1][c + 1] = nh0[c];
-#pragma unroll
-            for (int q = 0; q < YR - 1; ++q)
-#pragma unroll
-                for (int c = 0; c < C; ++c) FY[q][c] = FY[q + 1][c];
-#pragma unroll
-            for (int c = 0; c < C; ++c) FY[YR - 1][c] = ny0[c];
-        } else {
-#pragma unroll
-            for (int q = 0; q < HR - 1; ++q)
-#pragma unroll
-                for (int c = 0; c < C + 2; ++c) Hn[q][c] = Hn[q + 1][c];
-            Hn[HR - 1][0] = lane_from_left(nh0[C - 1]);
-            Hn[HR - 1][C + 1] = lane_from_right(nh0[0]);
-#pragma unroll
-            for (int c = 0; c < C; ++c) Hn[HR - 1][c + 1] = nh0[c];
-        }
-
-        // ---- levels 1..K: level t computes row r = j - t
-#pragma unroll
-        for (int t = 1; t <= K; ++t) {
-            const int r = j - t;
-            const bool rin = (r >= 1) && (r <= ny - 2);
-            const bool rown = (r >= r0) && (r < r1);
-            const T left = lane_from_left(U[t - 1][1][C - 1]);
-            const T right = lane_from_right(U[t - 1][1][0]);
-            T nu[C], nd[C], L[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const T uc = U[t - 1][1][c];
-                const T ue = (c < C - 1) ? U[t - 1][1][c + 1] : right;
-                const T uw = (c > 0) ? U[t - 1][1][c - 1] : left;
-                const T un = U[t - 1][2][c];
-                const T us = U[t - 1][0][c];
-                T fxe, fxw, fyn, fys;
-                if (FACE) {
-                    fxe = FX[K - t][c + 1];
-                    fxw = FX[K - t][c];
-                    fyn = FY[K + 1 - t][c];
-                    fys = FY[K - t][c];
-                } else {
-                    const int q = K + 1 - t;
-                    const T hc = Hn[q][c + 1];
-                    fxe = hc + Hn[q][c + 2];
-                    fxw = Hn[q][c] + hc;
-                    fyn = hc + Hn[q + 1][c + 1];
-                    fys = Hn[q - 1][c + 1] + hc;
-                }
-                L[c] = flux_L<T>(uc, ue, uw, un, us, fxe, fxw, fyn, fys, ax, ay);
-                const bool in = rin && colin[c];
-                nd[c] = in ? (D[t - 1][0][c] + L[c]) : T(0);
-                nu[c] = in ? (uc + nd[c]) : T(0);
-            }
-            if (want_energy && rown && lane_owned) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const double dd = (double)nd[c], uu = (double)nu[c], ll = (double)L[c];
-                    acc[t - 1] += __builtin_fma(-uu, ll, dd * dd);
-                }
-            }
-            if (want_trace && rown && rin) {
-                const int kb = M.rec_rowptr[r], ke = M.rec_rowptr[r + 1];
-                const int64_t row = n0 + t;
-                if (kb < ke && row < M.trace_rows) {
-                    for (int k = kb; k < ke; ++k) {
-                        const int col = M.rec_col[k];
-                        const int off = col - cb;
-                        if (lane_owned && off >= 0 && off < C) {
-                            T v = nu[0];
-#pragma unroll
-                            for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
-                            ((T*)M.traces)[row * M.R + M.rec_id[k]] = v;
-                        }
-                    }
-                }
-            }
-            if (t < K) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    U[t][0][c] = U[t][1][c];
-                    U[t][1][c] = U[t][2][c];
-                    U[t][2][c] = nu[c];
-                    D[t][0][c] = D[t][1][c];
-                    D[t][1][c] = nd[c];
-                }
-            } else if (rown && lane_owned) {
-                const size_t off = (size_t)r * ld + cb;
-                store_pack<T, C>(uout + off, nu);
-                store_pack<T, C>(dout + off, nd);
-            }
-        }
-    }
-
-    if (want_energy) {
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-            const double s = wave_sum(acc[t]);
-            if (lane == 0) M.epart[(size_t)t * M.epart_stride + wave] = s;
-        }
-    }
+    if (C == 2) return persistent_max_f64c2(K, face_mode);
+    return 0;
 }
-
-__device__ __forceinline__ int find_member(const MemberDev* table, int first, int nmembers, int gb)
-{
-    int m = first;
-    for (int k = first + 1; k < first + nmembers; ++k)
-        if (table[k].block_base <= gb) m = k;
-    return m;
-}
-
-template <typename T, int K, int FACE>
-__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step(StepArgs a)
-{
-    const int gb = xcd_remap(blockIdx.x, a.total_blocks) + a.block_offset;
-    const int m = find_member(a.table, a.first, a.nmembers, gb);
-    const MemberDev& M = a.table[m];
-    const int wave = (gb - M.block_base) * kWavesPerBlock + (threadIdx.x >> 6);
-    if (wave >= M.waves) return;
-    sweep_item<T, K, FACE>(M, wave, a.parity, a.ctx_step, a.want_energy, a.want_trace);
-}
-
-template <typename T, int K>
-static hipError_t launch_step_k(const StepArgs& a, int face_mode, int grid, hipStream_t s)
-{
-    if (face_mode == 1)
-        hipLaunchKernelGGL((k_step<T, K, 1>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step<T, K, 0>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_step(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s)
-{
-    switch (K) {
-    case 1: return launch_step_k<T, 1>(a, face_mode, grid, s);
-    case 2: return launch_step_k<T, 2>(a, face_mode, grid, s);
-    case 3: return launch_step_k<T, 3>(a, face_mode, grid, s);
-    case 4: return launch_step_k<T, 4>(a, face_mode, grid, s);
-    case 5: return launch_step_k<T, 5>(a, face_mode, grid, s);
-    case 6: return launch_step_k<T, 6>(a, face_mode, grid, s);
-    case 7: return launch_step_k<T, 7>(a, face_mode, grid, s);
-    case 8: return launch_step_k<T, 8>(a, face_mode, grid, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-template hipError_t launch_step<float>(const StepArgs&, int, int, int, hipStream_t);
-template hipError_t launch_step<double>(const StepArgs&, int, int, int, hipStream_t);
-
-// ------------------------------------------------------------------------------------------
-// Persistent batched variant: one cooperative launch runs `phases` time blocks of K steps
-// (plus a final block of tail_K steps) over all members, with a grid-wide barrier between
-// time blocks.  The barrier spin is bounded: on expiry it records an error flag and lets the
-// wave continue, so a launch always drains.
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
-{
-    // every wave publishes its own stores before the block arrives ...
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            long spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1L << 26)) {
-                    __hip_atomic_fetch_or(&bar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
-    }
-    gen += 1;
-    __syncthreads();
-    // ... and every wave sees the other blocks' stores afterwards
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-template <typename T, int K, int FACE>
-__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar)
-{
-    const int total_waves = a.total_blocks * kWavesPerBlock;  // work items of one time block
-    const int gw0 = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int stride = gridDim.x * kWavesPerBlock;
-    int gen = 0;
-    int parity = a.parity;
-    int64_t step = a.ctx_step;
-    for (int p = 0; p < phases; ++p) {
-        for (int item = gw0; item < total_waves; item += stride) {
-            const int gb = item / kWavesPerBlock + a.block_offset;
-            const int m = find_member(a.table, a.first, a.nmembers, gb);
-            const MemberDev& M = a.table[m];
-            const int wave = (gb - M.block_base) * kWavesPerBlock + (item % kWavesPerBlock);
-            if (wave < M.waves) sweep_item<T, K, FACE>(M, wave, parity, step, 0, 0);
-        }
-        parity ^= 1;
-        step += K;
-        if (p + 1 < phases) grid_barrier(bar, gridDim.x, gen);
-    }
-}
-
-template <typename T, int K>
-static hipError_t launch_persistent_k(const StepArgs& a, int face_mode, int phases, int grid, int* bar, hipStream_t s)
-{
-    void* args[] = {(void*)&a, (void*)&phases, (void*)&bar};
-    if (face_mode == 1)
-        return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, 1>, dim3(grid),
-                                          dim3(kWaveSize * kWavesPerBlock), args, 0, s);
-    return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, 0>, dim3(grid),
-                                      dim3(kWaveSize * kWavesPerBlock), args, 0, s);
-}
-
-template <typename T>
-hipError_t launch_step_persistent(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
-                                  hipStream_t s)
-{
-    switch (K) {
-    case 1: return launch_persistent_k<T, 1>(a, face_mode, phases, grid, bar, s);
-    case 2: return launch_persistent_k<T, 2>(a, face_mode, phases, grid, bar, s);
-    case 4: return launch_persistent_k<T, 4>(a, face_mode, phases, grid, bar, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-template hipError_t launch_step_persistent<float>(const StepArgs&, int, int, int, int, int*, hipStream_t);
-template hipError_t launch_step_persistent<double>(const StepArgs&, int, int, int, int, int*, hipStream_t);
-
-template <typename T>
-int persistent_max_blocks(int K, int face_mode)
-{
-    int per_cu = 0;
-    hipError_t e;
-    const int bs = kWaveSize * kWavesPerBlock;
-    if (K == 1)
-        e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 1, 1>, bs, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 1, 0>, bs, 0);
-    else if (K == 2)
-        e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 2, 1>, bs, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 2, 0>, bs, 0);
-    else
-        e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 4, 1>, bs, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, 4, 0>, bs, 0);
-    if (e != hipSuccess) return 0;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return per_cu * cus;
-}
-template int persistent_max_blocks<float>(int, int);
-template int persistent_max_blocks<double>(int, int);
 
 // ------------------------------------------------------------------------------------------
 // Energy finalisation: E = escale * sum over waves of the per-wave partials, fixed order.
@@ -555,7 +146,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* partials, in
 }
 
 // ------------------------------------------------------------------------------------------
-// a1: coefficient preparation.  Nodal layout: copy h (dense) into the pitched plane.  Face
+// Coefficient preparation.  Nodal layout: copy h (dense) into the pitched plane.  Face
 // layout: FX = h1_i + h1_{i+1}, FY = h2_j + h2_{j+1} (twice the face means).  Statistics for
 // validation and the stability check go to red[]: per block {min h, max hx face, max hy face,
 // non-finite count}.
@@ -680,7 +271,7 @@ template hipError_t launch_prepare_coeff<float>(const MemberDev*, const void*, c
 template hipError_t launch_prepare_coeff<double>(const MemberDev*, const void*, const void*, int, double*, hipStream_t);
 
 // ------------------------------------------------------------------------------------------
-// a2: start step.  du^1 = tau u1 + L(u^0)/2, u^1 = u^0 + du^1 (interior), written to pair 0;
+// Start step.  du^1 = tau u1 + L(u^0)/2, u^1 = u^0 + du^1 (interior), written to pair 0;
 // energy partials per block into red[], optional trace row 1.
 // ------------------------------------------------------------------------------------------
 template <typename T>
@@ -807,7 +398,7 @@ template hipError_t launch_state_energy<float>(const MemberDev*, int, double*, d
 template hipError_t launch_state_energy<double>(const MemberDev*, int, double*, double*, hipStream_t);
 
 // ------------------------------------------------------------------------------------------
-// a7: trace gather of one state row, and the FP64 misfit with its adjoint source.
+// Trace gather of one state row, and the FP64 misfit with its adjoint source.
 // ------------------------------------------------------------------------------------------
 template <typename T>
 __global__ void k_gather(const T* __restrict__ u, int ld, const int* __restrict__ rec_ij, int R, T* __restrict__ out)

@@ -1,0 +1,560 @@
+// fdw_stream.h - the streaming, temporally blocked leapfrog kernel (device code), included
+// by one instantiation unit per (storage type, columns per lane) so that the variants build
+// in parallel.  See fdw_kernels.hip for the overview of the method and its citations.
+#pragma once
+
+#include "fdw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace fdw {
+
+// ------------------------------------------------------------------------------------------
+// Lane exchange across the whole wave (DPP wave shift by one lane; lanes with no source get 0)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int lane_from_left_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // lane l <- lane l-1
+}
+__device__ __forceinline__ int lane_from_right_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // lane l <- lane l+1
+}
+__device__ __forceinline__ float lane_from_left(float v)
+{
+    return __builtin_bit_cast(float, lane_from_left_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float lane_from_right(float v)
+{
+    return __builtin_bit_cast(float, lane_from_right_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_from_left(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = lane_from_left_i((int)(b & 0xffffffffLL));
+    int hi = lane_from_left_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_right(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = lane_from_right_i((int)(b & 0xffffffffLL));
+    int hi = lane_from_right_i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ------------------------------------------------------------------------------------------
+// The point update, shared by every kernel that advances the state.
+//   f* are face sums (2x the face coefficient: h_c + h_neighbour), ax = tau^2/(2 dx^2).
+// Opposite faces are added as commutative pairs so that mirror-symmetric data stay
+// mirror-symmetric bit for bit.  The file is compiled without contraction; the one fused
+// multiply-add is explicit.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T flux_L(T uc, T ue, T uw, T un, T us, T fxe, T fxw, T fyn, T fys, T ax, T ay)
+{
+    T pe = fxe * (ue - uc);
+    T pw = fxw * (uw - uc);
+    T pn = fyn * (un - uc);
+    T ps = fys * (us - uc);
+    T sx = pe + pw;
+    T sy = pn + ps;
+    return __builtin_fma(ax, sx, ay * sy);
+}
+template <>
+__device__ __forceinline__ float flux_L<float>(float uc, float ue, float uw, float un, float us, float fxe, float fxw,
+                                               float fyn, float fys, float ax, float ay)
+{
+    float pe = fxe * (ue - uc);
+    float pw = fxw * (uw - uc);
+    float pn = fyn * (un - uc);
+    float ps = fys * (us - uc);
+    float sx = pe + pw;
+    float sy = pn + ps;
+    return __builtin_fmaf(ax, sx, ay * sy);
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T, int C>
+struct alignas(sizeof(T) * C) Pack {
+    T v[C];
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void load_pack(const T* __restrict__ p, T (&out)[C])
+{
+    Pack<T, C> q = *reinterpret_cast<const Pack<T, C>*>(p);
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = q.v[c];
+}
+template <typename T, int C>
+__device__ __forceinline__ void store_pack(T* __restrict__ p, const T (&in)[C])
+{
+    Pack<T, C> q;
+#pragma unroll
+    for (int c = 0; c < C; ++c) q.v[c] = in[c];
+    *reinterpret_cast<Pack<T, C>*>(p) = q;
+}
+
+template <typename T>
+struct Lanes;  // columns per lane: one 16-byte vector
+template <>
+struct Lanes<float> {
+    static constexpr int C = 4;
+};
+template <>
+struct Lanes<double> {
+    static constexpr int C = 2;
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give each
+    // XCD a contiguous range of logical blocks so that neighbouring strips share an L2.
+    int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+    return xcd * per + min(xcd, rem) + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// One streaming work item: member M, strip, segment; K time levels; C columns per lane.
+//
+// Level t (t = 1..K) computes row r = j - t at iteration j from level t-1's rows r and r+1
+// (u) and row r (du).  The x part of the operator is written with one flux per face,
+// F_c = fx_{c+1/2} (u_{c+1} - u_c), and the y part with the flux G_r = fy_{r+1/2}
+// (u_{r+1} - u_r) carried over from the previous row: sx = F_c - F_{c-1}, sy = G_r - G_{r-1}.
+// Since fx_{c-1/2}(u_{c-1} - u_c) = -F_{c-1} exactly, this is bit-identical to summing the
+// two opposite-face terms of every node.  Rings are indexed by the row modulo 2 and K; the
+// row loop is unrolled by lcm(2, K) so that every ring index is a compile-time constant.
+// The input row j+1 is loaded while row j is being processed.
+// ------------------------------------------------------------------------------------------
+template <int K>
+struct RowUnroll {
+    static constexpr int U = (K % 2 == 0) ? K : 2 * K;
+};
+__host__ __device__ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+// Row loads go through buffer resources: an offset at or beyond the resource's size returns
+// zeros in hardware, so rows above/below the grid and lanes outside the plane need no branch
+// (a load under a divergent branch would force the prefetch to be waited on at once).
+typedef unsigned int fdw_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int fdw_u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int fdw_u32x8 __attribute__((ext_vector_type(8)));
+constexpr unsigned int kBufferOutOfRange = 0x80000000u;  // offsets >= 2^31 are never valid
+constexpr int kBufferWord3 = 0x00020000;                // raw (untyped) buffer access, GFX9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferWord3);
+}
+
+// Loads the whole C-element vector; every element is consumed by the caller.
+template <typename T, int C>
+__device__ __forceinline__ void buffer_row(__amdgpu_buffer_rsrc_t r, unsigned int off, T (&out)[C])
+{
+    static_assert(sizeof(T) * C == 32 || sizeof(T) * C == 16 || sizeof(T) * C == 8, "8/16/32-byte lane vectors");
+    Pack<T, C> q;
+    if constexpr (sizeof(T) * C == 32) {
+        const fdw_u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        const fdw_u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + 16u), 0, 0);
+        const fdw_u32x8 v = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+        q = __builtin_bit_cast(Pack<T, C>, v);
+    } else if constexpr (sizeof(T) * C == 16) {
+        const fdw_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        q = __builtin_bit_cast(Pack<T, C>, v);
+    } else {
+        const fdw_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        q = __builtin_bit_cast(Pack<T, C>, v);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = q.v[c];
+}
+
+// MODE 0: plain steps; 1: per-step energy (traces recorded when `trace` is set); 2: traces only.
+// (The energy variants keep the trace path compiled in: without it the register allocator
+// of this toolchain produces a much larger footprint for some time blocks.)
+template <typename T, int K, int C, int FACE, int MODE>
+__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step, int trace)
+{
+    constexpr bool want_energy = MODE == 1;
+    const bool want_trace = (MODE == 2) || (MODE == 1 && trace != 0);
+    constexpr int Hx = ((K + C - 1) / C) * C;   // halo columns on each side (multiple of C)
+    constexpr int Wv = kWaveSize * C - 2 * Hx;  // owned columns per strip
+    constexpr int U = RowUnroll<K>::U;
+    const int lane = threadIdx.x & 63;
+
+    const int nx = M.nx, ny = M.ny, ld = M.ld;
+    const int strip = wave % M.strips;
+    const int seg = wave / M.strips;
+    const int cb = strip * Wv - Hx + lane * C;
+    const bool lane_live = (cb >= 0) && (cb < ld);
+    const bool lane_owned = lane_live && (lane * C >= Hx) && (lane * C < Hx + Wv);
+    T colm[C];  // 1 on interior columns, 0 on the boundary ring / padding
+#pragma unroll
+    for (int c = 0; c < C; ++c) colm[c] = ((cb + c >= 1) && (cb + c <= nx - 2)) ? T(1) : T(0);
+
+    const int r0 = seg * M.seg_rows;
+    const int r1 = min(r0 + M.seg_rows, ny);
+    const int cur = M.cur0 ^ parity;
+    const T* __restrict__ uin = (const T*)M.u[cur];
+    const T* __restrict__ din = (const T*)M.d[cur];
+    T* __restrict__ uout = (T*)M.u[cur ^ 1];
+    T* __restrict__ dout = (T*)M.d[cur ^ 1];
+    const T* __restrict__ hp = (const T*)M.h;
+    const T* __restrict__ hyp = (const T*)M.hy;
+    const T ax = (T)M.ax, ay = (T)M.ay;
+    const int64_t n0 = ctx_step + M.n_offset;
+
+    // buffer resources starting at the first streamed row inside the grid
+    const int jb = r0 - K;
+    const int jbase = max(jb, 0);
+    const size_t base_el = (size_t)jbase * ld;
+    const size_t span = (size_t)(ny - jbase) * ld * sizeof(T);
+    const unsigned int nbytes = (unsigned int)min(span, (size_t)kBufferOutOfRange - 16);
+    const __amdgpu_buffer_rsrc_t ru = plane_rsrc(uin + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(din + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rh = plane_rsrc(hp + base_el, nbytes);
+    const __amdgpu_buffer_rsrc_t rhy = plane_rsrc((FACE ? hyp : hp) + base_el, nbytes);
+    const unsigned int row_bytes = (unsigned int)(ld * (int)sizeof(T));
+    const unsigned int lane_col = lane_live ? (unsigned int)(cb * (int)sizeof(T)) : kBufferOutOfRange;
+
+    T Ur[K][2][C];  // level t at rows of parity 0/1 (relative to the first row jb)
+    T Dr[K][2][C];
+    T Gy[K][C];     // Gy[t-1]: y-flux of level t-1 below the row level t computes next
+    T FXr[K][C];    // x-face sums of the rows j-K .. j-1 (by row modulo K)
+    T FYr[K][C];    // y-face sums between those rows and the next
+    T hprev[C];     // coefficient row j-1 (nodal h, or the x-face row in the face layout)
+    T hyprev[C];    // face layout: y-face row j-1
+    T bu[2][C], bd[2][C], bh[2][C], bhy[2][C];  // loaded rows (double-buffered)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            Ur[t][0][c] = Ur[t][1][c] = T(0);
+            Dr[t][0][c] = Dr[t][1][c] = T(0);
+            Gy[t][c] = T(0);
+            FXr[t][c] = FYr[t][c] = T(0);
+        }
+        hprev[c] = hyprev[c] = T(0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) bu[q][c] = bd[q][c] = bh[q][c] = bhy[q][c] = T(0);
+    }
+    double acc[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) acc[t] = 0.0;
+
+    // Rows jb .. r1+K-1 are streamed (rounded up to whole unrolled blocks; rows outside the
+    // grid load as zeros and are never stored).
+    const int nblk = (r1 + K - jb + U - 1) / U;
+    const size_t lane_off = (size_t)(ptrdiff_t)cb;
+    auto load_row = [&](int j, T (&u)[C], T (&d)[C], T (&h)[C], T (&hy)[C]) {
+        const unsigned int off = (unsigned int)(j - jbase) * row_bytes + lane_col;
+        buffer_row<T, C>(ru, off, u);
+        buffer_row<T, C>(rd, off, d);
+        buffer_row<T, C>(rh, off, h);
+        if (FACE) buffer_row<T, C>(rhy, off, hy);
+    };
+    load_row(jb, bu[0], bd[0], bh[0], bhy[0]);
+
+    for (int blk = 0; blk < nblk; ++blk) {
+        T eb[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) eb[t] = T(0);
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            const int j = jb + blk * U + s;
+            const int pb = s & 1;  // buffer holding row j
+            // prefetch row j+1
+            load_row(j + 1, bu[pb ^ 1], bd[pb ^ 1], bh[pb ^ 1], bhy[pb ^ 1]);
+
+            // ---- coefficient faces of row j-1 into the ring (index (j-1-jb) mod K)
+            {
+                const int q = pmod(s - 1, K);
+                if (FACE) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        FXr[q][c] = hprev[c];
+                        FYr[q][c] = hyprev[c];
+                        hprev[c] = bh[pb][c];
+                        hyprev[c] = bhy[pb][c];
+                    }
+                } else {
+                    const T hr = lane_from_right(hprev[0]);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        FXr[q][c] = hprev[c] + ((c < C - 1) ? hprev[c + 1] : hr);
+                        FYr[q][c] = hprev[c] + bh[pb][c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
+                }
+            }
+            // ---- level 0: row j of the input state
+            {
+                const int p0 = pmod(s, 2);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    Ur[0][p0][c] = bu[pb][c];
+                    Dr[0][p0][c] = bd[pb][c];
+                }
+            }
+            // ---- levels 1..K
+#pragma unroll
+            for (int t = 1; t <= K; ++t) {
+                const int r = j - t;
+                const int pr = pmod(s - t, 2);      // parity index of row r
+                const int pr1 = pmod(s - t + 1, 2); // ... of row r+1
+                const int q = pmod(s - t, K);       // coefficient ring index of row r
+                const bool rin = (r >= 1) && (r <= ny - 2);
+                const bool rown = (r >= r0) && (r < r1);
+                const T right = lane_from_right(Ur[t - 1][pr][0]);
+                T F[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const T ue = (c < C - 1) ? Ur[t - 1][pr][c + 1] : right;
+                    F[c] = FXr[q][c] * (ue - Ur[t - 1][pr][c]);
+                }
+                const T Fl = lane_from_left(F[C - 1]);
+                T nu[C], nd[C], L[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const T Gn = FYr[q][c] * (Ur[t - 1][pr1][c] - Ur[t - 1][pr][c]);
+                    const T sx = F[c] - ((c > 0) ? F[c - 1] : Fl);
+                    const T sy = Gn - Gy[t - 1][c];
+                    Gy[t - 1][c] = Gn;
+                    L[c] = fma_t(ax, sx, ay * sy);
+                }
+                if (rin) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        nd[c] = fma_t(L[c], colm[c], Dr[t - 1][pr][c]);
+                        nu[c] = Ur[t - 1][pr][c] + nd[c];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) nd[c] = nu[c] = T(0);
+                }
+                if (want_energy && rown) {
+                    // per-node terms du^2 - u L in the storage type, summed over the lane's
+                    // columns and the rows of this unrolled block; FP64 across blocks
+                    T ps = T(0);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        ps = fma_t(nd[c], nd[c], ps);
+                        ps = fma_t(-nu[c], L[c], ps);
+                    }
+                    eb[t - 1] += ps;
+                }
+                if (want_trace && rown && rin) {
+                    const int kb = M.rec_rowptr[r], ke = M.rec_rowptr[r + 1];
+                    const int64_t row = n0 + t;
+                    if (kb < ke && row < M.trace_rows) {
+                        for (int k = kb; k < ke; ++k) {
+                            const int off = M.rec_col[k] - cb;
+                            if (lane_owned && off >= 0 && off < C) {
+                                T v = nu[0];
+#pragma unroll
+                                for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
+                                ((T*)M.traces)[row * M.R + M.rec_id[k]] = v;
+                            }
+                        }
+                    }
+                }
+                if (t < K) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        Ur[t][pr][c] = nu[c];
+                        Dr[t][pr][c] = nd[c];
+                    }
+                } else if (rown && lane_owned) {
+                    const size_t off = (size_t)(ptrdiff_t)r * ld + lane_off;
+                    store_pack<T, C>(uout + off, nu);
+                    store_pack<T, C>(dout + off, nd);
+                }
+            }
+            // keep the scheduler from interleaving consecutive rows (bounds register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (want_energy && lane_owned) {
+#pragma unroll
+            for (int t = 0; t < K; ++t) acc[t] += (double)eb[t];
+        }
+    }
+
+    if (want_energy) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const double sum = wave_sum(acc[t]);
+            if (lane == 0) M.epart[(size_t)t * M.epart_stride + wave] = sum;
+        }
+    }
+}
+
+__device__ __forceinline__ int find_member(const MemberDev* table, int first, int nmembers, int gb)
+{
+    int m = first;
+    for (int k = first + 1; k < first + nmembers; ++k)
+        if (table[k].block_base <= gb) m = k;
+    return m;
+}
+
+template <typename T, int K, int C, int FACE, int MODE>
+__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step(StepArgs a)
+{
+    const int gb = xcd_remap(blockIdx.x, a.total_blocks) + a.block_offset;
+    const int m = find_member(a.table, a.first, a.nmembers, gb);
+    const MemberDev& M = a.table[m];
+    const int wave = (gb - M.block_base) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wave >= M.waves) return;
+    sweep_item<T, K, C, FACE, MODE>(M, wave, a.parity, a.ctx_step, a.want_trace);
+}
+
+template <typename T, int K, int C, int FACE>
+static hipError_t launch_step_kcf(const StepArgs& a, int grid, hipStream_t s)
+{
+    const dim3 g(grid), b(kWaveSize * kWavesPerBlock);
+    if (a.want_energy)
+        hipLaunchKernelGGL((k_step<T, K, C, FACE, 1>), g, b, 0, s, a);
+    else if (a.want_trace)
+        hipLaunchKernelGGL((k_step<T, K, C, FACE, 2>), g, b, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step<T, K, C, FACE, 0>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int K, int C>
+static hipError_t launch_step_kc(const StepArgs& a, int face_mode, int grid, hipStream_t s)
+{
+    return face_mode == 1 ? launch_step_kcf<T, K, C, 1>(a, grid, s) : launch_step_kcf<T, K, C, 0>(a, grid, s);
+}
+
+// K = 1..KMAX of one (T, C) configuration
+template <typename T, int C, int KMAX>
+static hipError_t launch_step_c(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_step_kc<T, 1, C>(a, face_mode, grid, s);
+    case 2: return launch_step_kc<T, 2, C>(a, face_mode, grid, s);
+    case 3: return launch_step_kc<T, 3, C>(a, face_mode, grid, s);
+    case 4: return launch_step_kc<T, 4, C>(a, face_mode, grid, s);
+    case 5: return KMAX >= 5 ? launch_step_kc<T, (KMAX >= 5 ? 5 : 1), C>(a, face_mode, grid, s) : hipErrorInvalidValue;
+    case 6: return KMAX >= 6 ? launch_step_kc<T, (KMAX >= 6 ? 6 : 1), C>(a, face_mode, grid, s) : hipErrorInvalidValue;
+    case 7: return KMAX >= 7 ? launch_step_kc<T, (KMAX >= 7 ? 7 : 1), C>(a, face_mode, grid, s) : hipErrorInvalidValue;
+    case 8: return KMAX >= 8 ? launch_step_kc<T, (KMAX >= 8 ? 8 : 1), C>(a, face_mode, grid, s) : hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Persistent batched variant: one cooperative launch runs `phases` time blocks of K steps
+// (plus a final block of tail_K steps) over all members, with a grid-wide barrier between
+// time blocks.  The barrier spin is bounded: on expiry it records an error flag and lets the
+// wave continue, so a launch always drains.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
+{
+    // every wave publishes its own stores before the block arrives ...
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1L << 26)) {
+                    __hip_atomic_fetch_or(&bar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+    }
+    gen += 1;
+    __syncthreads();
+    // ... and every wave sees the other blocks' stores afterwards
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T, int K, int C, int FACE>
+__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar)
+{
+    const int total_waves = a.total_blocks * kWavesPerBlock;  // work items of one time block
+    const int gw0 = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int stride = gridDim.x * kWavesPerBlock;
+    int gen = 0;
+    int parity = a.parity;
+    int64_t step = a.ctx_step;
+    for (int p = 0; p < phases; ++p) {
+        for (int item = gw0; item < total_waves; item += stride) {
+            const int gb = item / kWavesPerBlock + a.block_offset;
+            const int m = find_member(a.table, a.first, a.nmembers, gb);
+            const MemberDev& M = a.table[m];
+            const int wave = (gb - M.block_base) * kWavesPerBlock + (item % kWavesPerBlock);
+            if (wave < M.waves) sweep_item<T, K, C, FACE, 0>(M, wave, parity, step, 0);
+        }
+        parity ^= 1;
+        step += K;
+        if (p + 1 < phases) grid_barrier(bar, gridDim.x, gen);
+    }
+}
+
+template <typename T, int K, int C>
+static hipError_t launch_persistent_kc(const StepArgs& a, int face_mode, int phases, int grid, int* bar, hipStream_t s)
+{
+    void* args[] = {(void*)&a, (void*)&phases, (void*)&bar};
+    if (face_mode == 1)
+        return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, C, 1>, dim3(grid),
+                                          dim3(kWaveSize * kWavesPerBlock), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, C, 0>, dim3(grid),
+                                      dim3(kWaveSize * kWavesPerBlock), args, 0, s);
+}
+
+template <typename T, int K, int C>
+static int persistent_blocks_kc(int face_mode)
+{
+    int per_cu = 0;
+    const int bs = kWaveSize * kWavesPerBlock;
+    hipError_t e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 1>, bs, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 0>, bs, 0);
+    if (e != hipSuccess) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+template <typename T, int C>
+static hipError_t launch_persistent_c(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                      hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_persistent_kc<T, 1, C>(a, face_mode, phases, grid, bar, s);
+    case 2: return launch_persistent_kc<T, 2, C>(a, face_mode, phases, grid, bar, s);
+    case 4: return launch_persistent_kc<T, 4, C>(a, face_mode, phases, grid, bar, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template <typename T, int C>
+static int persistent_max_c(int K, int face_mode)
+{
+    switch (K) {
+    case 1: return persistent_blocks_kc<T, 1, C>(face_mode);
+    case 2: return persistent_blocks_kc<T, 2, C>(face_mode);
+    case 4: return persistent_blocks_kc<T, 4, C>(face_mode);
+    default: return 0;
+    }
+}
+
+
+}  // namespace fdw

@@ -28,6 +28,7 @@ FDW_F32, FDW_F64 = 0, 1
 FDW_OK, FDW_EINVAL, FDW_ECFL, FDW_ESTATE, FDW_ENOMEM, FDW_EHIP, FDW_EUNSTABLE, FDW_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 FDW_ALLOW_UNSTABLE, FDW_ALLOW_ZERO_H = 1, 2
 FDW_CFG_TIME_BLOCK, FDW_CFG_SEGMENT_ROWS, FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE, FDW_CFG_TIMING = 1, 2, 3, 4, 5
+FDW_CFG_LANE_COLUMNS, FDW_CFG_ADJ_TIME_BLOCK, FDW_CFG_ADJ_LANE_COLUMNS = 6, 7, 8
 
 EXPORTED = [
     "fdw_workspace_bytes", "fdw_init", "fdw_set_coeff", "fdw_step_n", "fdw_energy", "fdw_record_traces",
@@ -256,10 +257,11 @@ class Solver:
         self._check(_lib.fdw_kernel_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
 
-    def autotune(self, steps: int = 0) -> Tuple[int, int]:
-        out = (ctypes.c_int64 * 2)()
+    def autotune(self, steps: int = 0) -> Tuple[int, int, int]:
+        """Returns (time_block, segment_rows, lane_columns)."""
+        out = (ctypes.c_int64 * 3)()
         self._check(_lib.fdw_autotune(self.ctx, int(steps), out))
-        return int(out[0]), int(out[1])
+        return int(out[0]), int(out[1]), int(out[2])
 
 
 def solver_for_case(case, dtype: int = FDW_F64, device: str = "cuda:0", flags: int = 0, separate_h2: bool = False):

@@ -1,4 +1,4 @@
-"""GPU adjoint (a7-a9) against the FP64 oracle's adjoint and against central finite
+"""GPU adjoint (traces, misfit, reverse sweep with checkpoints) against the FP64 oracle's adjoint and against central finite
 differences of the GPU forward, through the C-ABI; FdwMisfit autograd wrapper.
 
 Bar: gradient within 1e-6 relative (FP64) of the oracle and of central differences.

@@ -1,4 +1,4 @@
-"""Batched family of regularisations (a10): one launch per time block over all members, and
+"""Batched family of regularisations: one launch per time block over all members, and
 one persistent cooperative launch per step_n call.  Each member must equal its own
 single-member solve bit for bit, and the oracle within the FP64 / FP32 bars."""
 import sys
@@ -59,7 +59,7 @@ def test_batched_equals_single_and_oracle(dtype_name):
         for m, case in enumerate(fam):
             u1, du1, e1 = _single(case, dt, N, K=K, energy=True)
             assert np.array_equal(st[m][0], u1) and np.array_equal(st[m][1], du1), (K, m)
-            assert np.abs(E[m] - e1).max() <= 1e-13 * abs(e1[0])
+            assert np.abs(E[m] - e1).max() <= (1e-13 if dt == fdw.FDW_F64 else 1e-7) * abs(e1[0])
             ref = oracle.forward_case(case, want_energy=True)
             if dt == fdw.FDW_F64:
                 assert np.abs(st[m][0] - ref["u_cur"]).max() <= 1e-12

@@ -1,0 +1,90 @@
+"""Checks on the gfx950 assembly of this library's own kernels (compiled here from source).
+
+  * every buffer load in the streaming and reverse kernels has the width of the lane vector
+    (8/16 bytes): a narrower load would mean the compiler shrank a vector load, which this
+    toolchain can do wrongly when only some lanes of a loaded vector are used;
+  * the default variants of the streaming kernel do not spill to scratch;
+  * no scalar-cache stores or atomics, and no packed FP32 arithmetic, anywhere.
+"""
+import os
+import re
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2005_11931_amd", "csrc")
+UNITS = ["fdw_step_f32c2.hip", "fdw_step_f32c4.hip", "fdw_step_f64c2.hip", "fdw_adjoint.hip", "fdw_kernels.hip"]
+
+
+def _asm(unit, tmp):
+    out = os.path.join(tmp, unit + ".s")
+    cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--offload-device-only", "-S",
+           os.path.join(CSRC, unit), "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return open(out).read()
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    tmp = str(tmp_path_factory.mktemp("isa"))
+    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+        texts = list(ex.map(lambda u: _asm(u, tmp), UNITS))
+    return dict(zip(UNITS, texts))
+
+
+def _functions(text):
+    """name -> body of every kernel in an assembly file."""
+    out = {}
+    for m in re.finditer(r"^(_Z[^\s:]+):[^\n]*\n(.*?)^\.Lfunc_end", text, flags=re.M | re.S):
+        out[m.group(1)] = m.group(2)
+    return out
+
+
+def _meta(text, name):
+    m = re.search(r"\.amdhsa_kernel " + re.escape(name) + r"\n(.*?)\.end_amdhsa_kernel", text, flags=re.S)
+    return m.group(1) if m else ""
+
+
+@pytest.mark.slow
+def test_buffer_loads_have_lane_vector_width(asm):
+    expect = {"fdw_step_f32c2.hip": {"buffer_load_dwordx2"}, "fdw_step_f32c4.hip": {"buffer_load_dwordx4"},
+              "fdw_step_f64c2.hip": {"buffer_load_dwordx4"}}
+    for unit, widths in expect.items():
+        funcs = _functions(asm[unit])
+        assert funcs, unit
+        for name, body in funcs.items():
+            if "k_step" not in name:
+                continue
+            loads = set(re.findall(r"\b(buffer_load_\w+)", body))
+            assert loads and loads <= widths, (unit, name, loads)
+    # reverse sweep: float C=2 -> x2 (state) and x4 (FP64 gradient rows); double C=1 -> x2; C=2 -> x4
+    for name, body in _functions(asm["fdw_adjoint.hip"]).items():
+        if "k_adjoint" not in name or "seed" in name:
+            continue
+        loads = set(re.findall(r"\b(buffer_load_\w+)", body))
+        assert loads and loads <= {"buffer_load_dwordx2", "buffer_load_dwordx4"}, (name, loads)
+
+
+@pytest.mark.slow
+def test_default_stream_variants_do_not_spill(asm):
+    # float: 2 columns per lane, K = 4 (every mode); double: 2 columns, K = 2
+    wanted = [("fdw_step_f32c2.hip", "IfLi4ELi2E"), ("fdw_step_f64c2.hip", "IdLi2ELi2E")]
+    for unit, tag in wanted:
+        names = [n for n in _functions(asm[unit]) if "k_step" in n and tag in n and "persistent" not in n]
+        assert names, (unit, tag)
+        for n in names:
+            meta = _meta(asm[unit], n)
+            m = re.search(r"\.amdhsa_private_segment_fixed_size (\d+)", meta)
+            assert m and int(m.group(1)) == 0, (n, m and m.group(1))
+
+
+@pytest.mark.slow
+def test_no_scalar_cache_writes_or_packed_fp32(asm):
+    bad_scalar = re.compile(r"^\s+s_(store|atomic|buffer_store|scratch_store|dcache_wb)", re.M)
+    bad_pk = re.compile(r"^\s+v_pk_(add|mul|fma)_f32", re.M)
+    for unit, text in asm.items():
+        assert not bad_scalar.search(text), unit
+        assert not bad_pk.search(text), unit
