@@ -13,6 +13,10 @@ forward time ratio of the 2048^2 FP64 receiver-misfit gradient (4000 steps, chec
 oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
+       python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: one 400-step
+                        forward solve plus a 1 GiB device copy used to calibrate the counters)
+       python bench.py --summarize-profile DIR --out NAME (writes profiles/NAME.txt from the
+                        rocprofv3 stats/counter CSV files under DIR)
 """
 from __future__ import annotations
 
@@ -196,7 +200,88 @@ def cpu_baseline(I, budget_s=15.0):
                        f"including input copies ({dt:.1f} s wall)")
 
 
+def profile_run(dtype_name: str):
+    """Short, profiler-friendly run: a 1 GiB device-to-device copy (torch's copy kernel, known
+    size, for counter calibration) and one 400-step forward solve of the 8192^2 workload."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+    from paper_2005_11931_amd import inputs as I
+
+    n_bytes = 1 << 30
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 copies of", n_bytes, "bytes")
+    del a, b
+    dtype = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
+    case = I.point_case(n=8192, nsteps=5000)
+    s = fdw.solver_for_case(case, dtype=dtype)
+    s.step(400, energy=True)
+    torch.cuda.synchronize()
+    log("profile run done:", dtype_name, "K", s.config(fdw.FDW_CFG_TIME_BLOCK), "C",
+        s.config(fdw.FDW_CFG_LANE_COLUMNS), "S", s.config(fdw.FDW_CFG_SEGMENT_ROWS))
+    s.close()
+
+
+def summarize_profile(d: str, name: str, command: str):
+    """Collects kernel statistics and (if present) FETCH_SIZE / WRITE_SIZE counter rows from
+    rocprofv3 CSV output under d into profiles/<name>.txt."""
+    import csv
+    import glob
+
+    lines = [f"# {name}", f"command: {command}", ""]
+    stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
+    for f in stats:
+        rows = list(csv.DictReader(open(f)))
+        lines.append(f"kernel stats ({os.path.relpath(f, d)}):")
+        lines.append("name | calls | total_ns | avg_ns | pct")
+        for r in rows[:12]:
+            lines.append(f"{r.get('Name','')[:90]} | {r.get('Calls','')} | {r.get('TotalDurationNs','')} | "
+                         f"{r.get('AverageNs','')} | {r.get('Percentage','')}")
+        lines.append("")
+    counters = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    summary = {}
+    for f in counters:
+        for r in csv.DictReader(open(f)):
+            kname = r.get("Kernel_Name", "")
+            cname = r.get("Counter_Name", "")
+            try:
+                val = float(r.get("Counter_Value", "nan"))
+            except ValueError:
+                continue
+            key = ("copy" if ("copy" in kname.lower() or "elementwise" in kname.lower()) else
+                   ("k_step" if "k_step" in kname else None))
+            if key is None:
+                continue
+            summary.setdefault((key, cname), []).append(val)
+    if summary:
+        lines.append("counters (per dispatch, mean over dispatches):")
+        for (k, c), v in sorted(summary.items()):
+            lines.append(f"{k} {c} mean {sum(v) / len(v):.1f} KiB over {len(v)} dispatches")
+    out = os.path.join(ROOT, "profiles", name + ".txt")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print(out)
+
+
 def main():
+    if "--summarize-profile" in sys.argv:
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--summarize-profile", required=True)
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--command", default="")
+        a = ap.parse_args()
+        summarize_profile(a.summarize_profile, a.out, a.command)
+        return
+    if "--profile-run" in sys.argv:
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--profile-run", action="store_true")
+        ap.add_argument("--dtype", default="f32")
+        a = ap.parse_args()
+        profile_run(a.dtype)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)

@@ -147,6 +147,11 @@ int fdw_get_state(fdw_ctx* ctx, int32_t member, void* u, void* du, int64_t* n);
  * n >= 1 (at n = 0 the state is defined by the initial data). */
 int fdw_set_state(fdw_ctx* ctx, int32_t member, const void* u, const void* du, int64_t n);
 
+/* L2 distance of two members' current fields, sqrt(dx dy sum (u_a - u_b)^2) in double, for
+ * comparing regularisations on the same grid (the limit eps -> 0 of Section 3.2).  Both
+ * members must have the same nx, ny and domain; synchronises the stream; result on the host. */
+int fdw_member_distance(fdw_ctx* ctx, int32_t member_a, int32_t member_b, double* dist_host);
+
 /* Return member m to step 0 (its initial data). */
 int fdw_reset(fdw_ctx* ctx, int32_t member);
 

@@ -786,6 +786,30 @@ int fdw_set_state(fdw_ctx* c, int32_t m, const void* u, const void* du, int64_t 
     return push_member(c, m);
 }
 
+int fdw_member_distance(fdw_ctx* c, int32_t a, int32_t b, double* dist_host)
+{
+    int rc = check_member(c, a);
+    if (rc) return rc;
+    rc = check_member(c, b);
+    if (rc) return rc;
+    if (!dist_host) return fail(c, FDW_EINVAL, "dist_host is NULL");
+    const HostMember& A = c->m[a];
+    const HostMember& B = c->m[b];
+    if (A.nx != B.nx || A.ny != B.ny || A.p.x0 != B.p.x0 || A.p.x1 != B.p.x1 || A.p.y0 != B.p.y0 ||
+        A.p.y1 != B.p.y1)
+        return fail(c, FDW_EINVAL, "members differ in grid or domain");
+    const void* ua = (A.n == 0) ? A.u0 : A.u[A.cur];
+    const void* ub = (B.n == 0) ? B.u0 : B.u[B.cur];
+    const double scale = A.dx * A.dy;
+    HIPCHK(c, (c->dtype == FDW_F32) ? launch_diff_norm<float>(ua, ub, A.ld, A.nx, A.ny, scale, c->red, c->scal, c->stream)
+                                    : launch_diff_norm<double>(ua, ub, A.ld, A.nx, A.ny, scale, c->red, c->scal, c->stream));
+    double sq = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&sq, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *dist_host = std::sqrt(sq);
+    return FDW_OK;
+}
+
 int fdw_reset(fdw_ctx* c, int32_t m)
 {
     int rc = check_member(c, m);

@@ -94,6 +94,9 @@ hipError_t launch_copy_in(const void* src, int nx, int ny, void* dst, int ld, in
 template <typename T>
 hipError_t launch_copy_out(const void* src, int ld, int nx, int ny, void* dst, hipStream_t s);
 hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s);
+template <typename T>
+hipError_t launch_diff_norm(const void* a, const void* b, int ld, int nx, int ny, double scale, double* red,
+                            double* out, hipStream_t s);
 hipError_t launch_receivers_csr(const int* rec_ij, int R, int nx, int ny, int* rowptr, int* col, int* id,
                                 int* status, hipStream_t s);
 

@@ -447,6 +447,41 @@ template hipError_t launch_misfit<float>(const void*, const double*, int64_t, do
 template hipError_t launch_misfit<double>(const void*, const double*, int64_t, double*, double*, double*, hipStream_t);
 
 // ------------------------------------------------------------------------------------------
+// Squared L2 distance of two fields (FP64 accumulation, fixed order).
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_diff_norm(const T* __restrict__ a, const T* __restrict__ b, int ld, int nx,
+                                                   int64_t total, double* red)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256) {
+        if ((int)(k % ld) >= nx) continue;
+        const double d = (double)a[k] - (double)b[k];
+        acc += d * d;
+    }
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = sum;
+}
+template <typename T>
+hipError_t launch_diff_norm(const void* a, const void* b, int ld, int nx, int ny, double scale, double* red,
+                            double* out, hipStream_t s)
+{
+    const int64_t total = (int64_t)ld * ny;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > kRedBlocks) blocks = kRedBlocks;
+    hipLaunchKernelGGL((k_diff_norm<T>), dim3(blocks), dim3(256), 0, s, (const T*)a, (const T*)b, ld, nx, total, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, red, blocks, scale, out);
+    return hipGetLastError();
+}
+template hipError_t launch_diff_norm<float>(const void*, const void*, int, int, int, double, double*, double*,
+                                            hipStream_t);
+template hipError_t launch_diff_norm<double>(const void*, const void*, int, int, int, double, double*, double*,
+                                             hipStream_t);
+
+// ------------------------------------------------------------------------------------------
 // Layout conversion: dense caller arrays <-> pitched planes (boundary ring zeroed on input).
 // ------------------------------------------------------------------------------------------
 template <typename T>

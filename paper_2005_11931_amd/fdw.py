@@ -33,6 +33,7 @@ FDW_CFG_LANE_COLUMNS, FDW_CFG_ADJ_TIME_BLOCK, FDW_CFG_ADJ_LANE_COLUMNS = 6, 7, 8
 EXPORTED = [
     "fdw_workspace_bytes", "fdw_init", "fdw_set_coeff", "fdw_step_n", "fdw_energy", "fdw_record_traces",
     "fdw_misfit", "fdw_adjoint_workspace_bytes", "fdw_adjoint", "fdw_get_state", "fdw_set_state", "fdw_reset",
+    "fdw_member_distance",
     "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_kernel_time", "fdw_last_error",
     "fdw_status_string", "fdw_destroy",
 ]
@@ -65,6 +66,8 @@ _lib.fdw_adjoint.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctyp
 _lib.fdw_get_state.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.fdw_set_state.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64]
 _lib.fdw_reset.argtypes = [_vp, ctypes.c_int32]
+_lib.fdw_member_distance.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+_lib.fdw_member_distance.restype = ctypes.c_int
 _lib.fdw_steps_taken.argtypes = [_vp, ctypes.c_int32]
 _lib.fdw_steps_taken.restype = ctypes.c_int64
 _lib.fdw_configure.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
@@ -237,6 +240,12 @@ class Solver:
         u, du = u.contiguous(), du.contiguous()
         self._check(_lib.fdw_set_state(self.ctx, member, _ptr(u), _ptr(du), int(n)))
         torch.cuda.current_stream(self.device).synchronize()
+
+    def distance(self, a: int, b: int) -> float:
+        """L2 distance sqrt(dx dy sum (u_a - u_b)^2) of two members' current fields."""
+        out = ctypes.c_double()
+        self._check(_lib.fdw_member_distance(self.ctx, a, b, ctypes.byref(out)))
+        return float(out.value)
 
     def reset(self, member: int = 0):
         self._check(_lib.fdw_reset(self.ctx, member))

@@ -93,6 +93,12 @@ def friedrichs(x: np.ndarray, eps: float = 1.0) -> np.ndarray:
     return friedrichs_constant() * _friedrichs_unnormalised(np.asarray(x) / eps) / eps
 
 
+def _bump_kernel(s: float) -> float:
+    """exp(1/(s^2-1)) on (-1, 1), 0 where s^2 rounds to 1 or beyond."""
+    q = s * s - 1.0
+    return math.exp(1.0 / q) if q < 0.0 else 0.0
+
+
 def heaviside_friedrichs(x: np.ndarray, eps: float) -> np.ndarray:
     """Heaviside step convolved with the Friedrichs phi_eps, i.e. the integral of phi_eps up to x."""
     from scipy.integrate import quad
@@ -108,7 +114,7 @@ def heaviside_friedrichs(x: np.ndarray, eps: float) -> np.ndarray:
         elif t >= 1.0:
             flat_out[k] = 1.0
         else:
-            v, _ = quad(lambda s: math.exp(1.0 / (s * s - 1.0)), -1.0, t, epsabs=1e-15, epsrel=1e-13, limit=200)
+            v, _ = quad(_bump_kernel, -1.0, t, epsabs=1e-15, epsrel=1e-13, limit=200)
             flat_out[k] = c * v
     return out
 
@@ -365,7 +371,7 @@ def bathymetry_case(n: int = 16384, nsteps: int = 10000, cfl: float = 0.5, seeds
     u0 = zero_ring(humps(X, Y, centres, 0.02))
     tau = cfl_tau(dx, float(h.max()), cfl)
     return Case(name, n, n, -1.0, 1.0, -1.0, 1.0, tau, nsteps, h, None, u0, np.zeros_like(u0),
-                meta=dict(eps=eps, seeds=list(seeds), hmax=float(h.max())))
+                meta=dict(eps=eps, seeds=list(seeds), hmax=float(h.max()), centres=centres.tolist()))
 
 
 # --------------------------------------------------------------------------------------
@@ -400,3 +406,40 @@ def row_mode_case(x: np.ndarray, h: np.ndarray, u0: np.ndarray, tau: float, nste
     U0 = zero_ring(U0)
     dy = 1.0
     return Case(name, n, 3, float(x[0]), float(x[-1]), 0.0, 2.0 * dy, tau, nsteps, H1, H2, U0, np.zeros_like(U0))
+
+
+def paper_1d_case(kind: str = "jump", eps: float = 0.2, dx: float = 0.005, T: float = 5.0, amp: float = 1.0,
+                  u0_kind: str = "gauss", e: float = 0.5, cfl: float = 0.5) -> Case:
+    """Section 3.1 / 3.2.3 in row mode: (0, 100) with spacing dx, the regularised depth of
+    paper_depth_1d, u0 = 40 exp(-(x-40)^2/8) ("gauss", Section 3.1) or e/((x-60)^2+e^2)
+    ("lorentz", Section 3.2.3), u1 = 0, tau = cfl dx / sqrt(max h), horizon T."""
+    n = int(round(100.0 / dx)) + 1
+    x = node_coords(n, 0.0, 100.0)
+    h = paper_depth_1d(x, eps, kind, amp=amp)
+    if u0_kind == "gauss":
+        g = 40.0 * np.exp(-((x - 40.0) ** 2) / 8.0)
+    else:
+        g = e / ((x - 60.0) ** 2 + e * e)
+    g[0] = g[-1] = 0.0
+    tau0 = cfl * (x[1] - x[0]) / math.sqrt(float(h.max()))
+    N = int(math.ceil(T / tau0))
+    c = row_mode_case(x, h, g, T / N, N, name=f"paper1d-{kind}")
+    c.meta.update(kind=kind, eps=eps, amp=amp, u0=u0_kind, e=e)
+    return c
+
+
+def paper_2d_case(eps: float = 0.8, dx: float = 0.05, T: float = 5.0, cfl: float = 0.5) -> Case:
+    """Section 3.3: [0, 100]^2, H_eps(x, y) = h_{0,eps}(x) (100 | 10 at x = 75, Friedrichs
+    mollified), u0 = 50 exp(-((x-40)^2 + (y-50)^2)/8), u1 = 0, zero Dirichlet data,
+    tau = cfl dx / sqrt(max h) (the paper's own implicit run uses dt = 0.5)."""
+    n = int(round(100.0 / dx)) + 1
+    x = node_coords(n, 0.0, 100.0)
+    hx = paper_depth_1d(x, eps, "jump")
+    H = np.broadcast_to(hx[None, :], (n, n)).copy()
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = zero_ring(50.0 * np.exp(-((X - 40.0) ** 2 + (Y - 50.0) ** 2) / 8.0))
+    tau0 = cfl * dx / math.sqrt(float(hx.max()))
+    N = int(math.ceil(T / tau0))
+    return Case("paper2d", n, n, 0.0, 100.0, 0.0, 100.0, T / N, N, H, None, u0, np.zeros_like(u0),
+                meta=dict(eps=eps))
+
