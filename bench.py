@@ -42,7 +42,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("fdw_kernels.hip", "fdw_internal.h"):
+    for f in ("fdw_stream.h", "fdw_step_f32c2.hip", "fdw_step_f32c4.hip", "fdw_internal.h"):
         with open(os.path.join(ROOT, "paper_2005_11931_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -169,10 +169,25 @@ def adjoint_bench(fdw, torch, I, steps, warmup):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    # checkpoints stored by the forward run itself: the adjoint then skips its replay
+    ws2 = torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+    def fwd_rec():
+        s.reset()
+        s._check(fdw.lib().fdw_record_checkpoints(s.ctx, 0, 64, fdw._ptr(ws2), nb))
+        s.step(N)
+
+    def adj_rec():
+        s._check(fdw.lib().fdw_adjoint(s.ctx, 0, fdw._ptr(recd), recd.shape[0], fdw._ptr(tg), 64, fdw._ptr(ws2), nb,
+                                       fdw._ptr(g), None))
+
     tf = timed(fwd)
     ta = timed(adj)
+    tfr = timed(fwd_rec)
+    tar = timed(adj_rec)
     s.close()
-    return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, n=case.nx, nsteps=N)
+    return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, forward_recording_s=tfr, adjoint_recorded_s=tar,
+                ratio_recorded=tar / tf, gradient_ratio=(tfr + tar) / tf, n=case.nx, nsteps=N)
 
 
 def cpu_baseline(I, budget_s=15.0):
@@ -370,8 +385,15 @@ def main():
         log(json.dumps(adj))
         out["adjoint"] = {"ratio": round(adj["ratio"], 3), "forward_ms": round(adj["forward_s"] * 1e3, 2),
                           "adjoint_ms": round(adj["adjoint_s"] * 1e3, 2),
+                          "ratio_recorded": round(adj["ratio_recorded"], 3),
+                          "forward_recording_ms": round(adj["forward_recording_s"] * 1e3, 2),
+                          "adjoint_recorded_ms": round(adj["adjoint_recorded_s"] * 1e3, 2),
+                          "gradient_ratio": round(adj["gradient_ratio"], 3),
                           "workload": "2048x2048 FP64 receiver-misfit gradient, 4000 steps, 64 receivers, "
-                                      "checkpoints every 64 steps"}
+                                      "checkpoints every 64 steps; ratio: adjoint call with its own forward replay "
+                                      "/ forward solve; ratio_recorded: adjoint call from checkpoints stored by the "
+                                      "forward solve / forward solve; gradient_ratio: (forward solve storing "
+                                      "checkpoints + adjoint from them) / forward solve"}
     if not args.skip_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(I)

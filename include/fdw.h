@@ -126,11 +126,24 @@ int fdw_misfit(fdw_ctx* ctx, int32_t member, const void* traces, const double* d
  * ckpt_every steps. */
 size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t ckpt_every);
 
+/* Store the adjoint's checkpoints during member m's forward run: from step 0 on, every
+ * fdw_step_n writes (u^n, du^n) for n = ckpt_every, 2 ckpt_every, ... < N into adj_ws
+ * (device, at least fdw_adjoint_workspace_bytes(member, ckpt_every) bytes, 256-byte aligned,
+ * owned by the caller and kept alive while recording).  Time blocks are cut at those steps;
+ * graph capture and the persistent batch launch are not used while recording.  A later
+ * fdw_adjoint of member m with the same adj_ws and ckpt_every, once the member stands at
+ * step N, then skips its forward replay.  Needs the member at step 0 (FDW_ESTATE otherwise);
+ * fdw_set_coeff, fdw_reset and fdw_set_state of the member stop the recording, as does a call
+ * with adj_ws = NULL.  One member per context records at a time (a new call replaces the old). */
+int fdw_record_checkpoints(fdw_ctx* ctx, int32_t member, int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes);
+
 /* Gradient with respect to the nodal coefficient(s) of a loss L of the traces u^k_r,
- * k = 0..N: the forward recurrence is replayed from member m's initial data
- * storing the state every ckpt_every steps, then the transposed (reverse leapfrog)
- * recurrence runs backwards, each segment being reconstructed from its checkpoint by time
- * reversal.  trace_grad: device double [N+1][R] = dL/du^k at the receivers;
+ * k = 0..N, by the discrete adjoint of the leapfrog scheme of fdw_step_n: the
+ * forward recurrence is replayed from member m's initial data storing the state every
+ * ckpt_every steps (skipped when fdw_record_checkpoints recorded them during the forward run
+ * that left the member at step N), then the transposed (reverse leapfrog) recurrence runs
+ * backwards, each segment being reconstructed from its checkpoint by time reversal.
+ * trace_grad: device double [N+1][R] = dL/du^k at the receivers;
  * recv_ij: device int32 [R][2] (interior nodes); adj_ws: device workspace of
  * fdw_adjoint_workspace_bytes() bytes; grad_h1: device double [ny][nx] receives dL/dh1;
  * grad_h2: device double [ny][nx] receives dL/dh2, or NULL to receive dL/dh1 + dL/dh2 in
@@ -173,9 +186,10 @@ enum {
     FDW_CFG_BATCH_MODE = 4,
     FDW_CFG_TIMING = 5, /* 1: bracket every stencil launch with HIP events (see fdw_kernel_time) */
     FDW_CFG_LANE_COLUMNS = 6, /* grid columns per lane of the streaming kernels: 2 or 4 (float), 2 (double); 0 = default */
-    FDW_CFG_ADJ_TIME_BLOCK = 7,  /* reverse steps per launch of the adjoint sweep, 1..4 (0 = 2) */
-    FDW_CFG_ADJ_LANE_COLUMNS = 8 /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
-                                    0 = default (2 for float, 1 for double) */
+    FDW_CFG_ADJ_TIME_BLOCK = 7,  /* reverse steps per launch of the adjoint sweep, 1..4 (0 = 4) */
+    FDW_CFG_ADJ_LANE_COLUMNS = 8, /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
+                                     0 = default (2 for float, 1 for double) */
+    FDW_CFG_ADJ_SEGMENT_ROWS = 9  /* rows per work item of the adjoint sweep, 16..4096 (0 = automatic) */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);

@@ -34,15 +34,16 @@ namespace fdw {
 // (x fluxes per face, y flux carried from the row above).  The gradient terms are products
 // of the face differences, Px = (u_{c+1}-u_c)(lam_{c+1}-lam_c), each shared by the face's two
 // nodes; a node collects its K levels in registers and its accumulator plane is updated once
-// per launch.
-template <typename T, int K, int C, int FACE>
+// per launch.  SPLIT keeps the x and y parts (dJ/dh1, dJ/dh2) in separate planes; otherwise
+// one plane holds their sum.
+template <typename T, int K, int C, int FACE, int SPLIT>
 __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs a)
 {
     constexpr int Hx = ((K + C - 1) / C) * C;
     constexpr int Wv = kWaveSize * C - 2 * Hx;
     constexpr int U = RowUnroll<K>::U;
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
     if (wave >= a.waves) return;
 
     const int nx = a.nx, ny = a.ny, ld = a.ld;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     const int r1 = min(r0 + a.seg_rows, ny);
     const T ax = (T)a.ax, ay = (T)a.ay;
     const double axd = a.ax, ayd = a.ay;
-    const bool split = (a.g2 != a.g1);
+    constexpr bool split = SPLIT != 0;
 
     const int jb = r0 - K;
     const int jbase = max(jb, 0);
@@ -80,6 +81,14 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     const __amdgpu_buffer_rsrc_t rg2 = plane_rsrc(a.g2 + base_el, gbytes);
     const unsigned int grow_bytes = (unsigned int)(ld * (int)sizeof(double));
     const unsigned int glane_col = lane_owned ? (unsigned int)(cb * (int)sizeof(double)) : kBufferOutOfRange;
+    // receiver CSR (row pointers, columns, ids) and the trace gradient are not written during
+    // the launch: read them as constant memory, so that their (wave-uniform) lookups are scalar
+    // loads and do not wait behind the vector loads of the row prefetch
+    const ConstPtr<int> rowptr = (ConstPtr<int>)a.rec_rowptr;
+    const ConstPtr<int> rcol = (ConstPtr<int>)a.rec_col;
+    const ConstPtr<int> rid = (ConstPtr<int>)a.rec_id;
+    const ConstPtr<double> tgrad = (ConstPtr<double>)a.trace_grad;
+    const bool any_rec = a.R > 0;
     T* __restrict__ uout = (T*)a.uout;
     T* __restrict__ dout = (T*)a.dout;
     T* __restrict__ lout = (T*)a.lout;
@@ -92,10 +101,16 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     T Gu[K][C];         // y flux of u^{m-s} below row r (level s stores at s-1)
     T Gl[K][C];         // y flux of lam^{m-s+1} below row r
     double Py[K][C];    // y face products below row r
-    double GX[K][C], GY[K][C];  // gradient of rows j-1 .. j-K (by row modulo K)
+    double GX[K][C], GY[K][C];  // gradient of rows j-1 .. j-K (by row modulo K); GY only if SPLIT
+    double gbuf[2][C], g2buf[2][C];  // accumulator rows loaded one iteration ahead
     T FXr[K][C], FYr[K][C];
     T hprev[C], hyprev[C];
     T bu[2][C], bd[2][C], bl[2][C], bm[2][C], bh[2][C], bhy[2][C];
+    // receiver range [RPb, RPe) of the rows j-1 .. j-K (by row modulo K), looked up once per
+    // row when it enters level 1
+    int RPb[K], RPe[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) RPb[t] = RPe[t] = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
 #pragma unroll
@@ -109,7 +124,10 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
         }
         hprev[c] = hyprev[c] = T(0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) bu[q][c] = bd[q][c] = bl[q][c] = bm[q][c] = bh[q][c] = bhy[q][c] = T(0);
+        for (int q = 0; q < 2; ++q) {
+            bu[q][c] = bd[q][c] = bl[q][c] = bm[q][c] = bh[q][c] = bhy[q][c] = T(0);
+            gbuf[q][c] = g2buf[q][c] = 0.0;
+        }
     }
     auto load_row = [&](int j, T (&u)[C], T (&d)[C], T (&l)[C], T (&m)[C], T (&h)[C], T (&hy)[C]) {
         const unsigned int off = (unsigned int)(j - jbase) * row_bytes + lane_col;
@@ -120,7 +138,14 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
         buffer_row<T, C>(rh, off, h);
         if (FACE) buffer_row<T, C>(rhy, off, hy);
     };
+    // accumulator row j-K+1 ... of the row completed one iteration later
+    auto load_g = [&](int j, double (&g1)[C], double (&g2)[C]) {
+        const unsigned int goff = (unsigned int)(j - jbase) * grow_bytes + glane_col;
+        buffer_row<double, C>(rg1, goff, g1);
+        if (split) buffer_row<double, C>(rg2, goff, g2);
+    };
     load_row(jb, bu[0], bd[0], bl[0], bm[0], bh[0], bhy[0]);
+    load_g(jb - K, gbuf[0], g2buf[0]);
     const int nblk = (r1 + K - jb + U - 1) / U;
 
     for (int blk = 0; blk < nblk; ++blk) {
@@ -129,13 +154,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
             const int j = jb + blk * U + s;
             const int pb = s & 1;
             load_row(j + 1, bu[pb ^ 1], bd[pb ^ 1], bl[pb ^ 1], bm[pb ^ 1], bh[pb ^ 1], bhy[pb ^ 1]);
-            // gradient accumulator of the row completed at the end of this iteration
-            double g1old[C], g2old[C];
-            {
-                const unsigned int goff = (unsigned int)(j - K - jbase) * grow_bytes + glane_col;
-                buffer_row<double, C>(rg1, goff, g1old);
-                if (split) buffer_row<double, C>(rg2, goff, g2old);
-            }
+            load_g(j + 1 - K, gbuf[pb ^ 1], g2buf[pb ^ 1]);
             // coefficient faces of row j-1
             {
                 const int q = pmod(s - 1, K);
@@ -216,7 +235,10 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     const double gy = Pyn + Py[t - 1][c];
                     Py[t - 1][c] = Pyn;
                     GX[q][c] = __builtin_fma(-w * axd, gx, GX[q][c]);
-                    GY[q][c] = __builtin_fma(-w * ayd, gy, GY[q][c]);
+                    if (split)
+                        GY[q][c] = __builtin_fma(-w * ayd, gy, GY[q][c]);
+                    else
+                        GX[q][c] = __builtin_fma(-w * ayd, gy, GX[q][c]);
                     if (rin) {
                         nd[c] = fma_t(-Lu, colm[c], Dr[t - 1][pr][c]);
                         nm[c] = fma_t(Ll, colm[c], Mr[t - 1][pr][c]);
@@ -224,12 +246,16 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                         nd[c] = nm[c] = T(0);
                     }
                 }
-                if (a.R > 0 && rin) {
-                    const int kb = a.rec_rowptr[r], ke = a.rec_rowptr[r + 1];
+                if (t == 1 && any_rec) {
+                    RPb[q] = rin ? rowptr[r] : 0;
+                    RPe[q] = rin ? rowptr[r + 1] : 0;
+                }
+                if (any_rec && rin) {
+                    const int kb = RPb[q], ke = RPe[q];
                     for (int k = kb; k < ke; ++k) {
-                        const int off = a.rec_col[k] - cb;
+                        const int off = rcol[k] - cb;
                         if (off >= 0 && off < C) {
-                            const T sv = (T)a.trace_grad[n * a.R + a.rec_id[k]];
+                            const T sv = (T)tgrad[n * a.R + rid[k]];
 #pragma unroll
                             for (int c = 0; c < C; ++c)
                                 if (off == c) nm[c] += sv;
@@ -265,12 +291,8 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     double o1[C], o2[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        if (split) {
-                            o1[c] = g1old[c] + GX[qd][c];
-                            o2[c] = g2old[c] + GY[qd][c];
-                        } else {
-                            o1[c] = g1old[c] + (GX[qd][c] + GY[qd][c]);
-                        }
+                        o1[c] = gbuf[pb][c] + GX[qd][c];
+                        o2[c] = g2buf[pb][c] + GY[qd][c];
                     }
                     store_pack<double, C>(a.g1 + off, o1);
                     if (split) store_pack<double, C>(a.g2 + off, o2);
@@ -286,10 +308,16 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
 template <typename T, int K, int C>
 static hipError_t adj_launch_kc(const AdjArgs& a, int grid, hipStream_t s)
 {
-    if (a.face)
-        hipLaunchKernelGGL((k_adjoint<T, K, C, 1>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
+    const dim3 g(grid), b(kWaveSize * kWavesPerBlock);
+    const bool split = a.g2 != a.g1;
+    if (a.face && split)
+        hipLaunchKernelGGL((k_adjoint<T, K, C, 1, 1>), g, b, 0, s, a);
+    else if (a.face)
+        hipLaunchKernelGGL((k_adjoint<T, K, C, 1, 0>), g, b, 0, s, a);
+    else if (split)
+        hipLaunchKernelGGL((k_adjoint<T, K, C, 0, 1>), g, b, 0, s, a);
     else
-        hipLaunchKernelGGL((k_adjoint<T, K, C, 0>), dim3(grid), dim3(kWaveSize * kWavesPerBlock), 0, s, a);
+        hipLaunchKernelGGL((k_adjoint<T, K, C, 0, 0>), g, b, 0, s, a);
     return hipGetLastError();
 }
 

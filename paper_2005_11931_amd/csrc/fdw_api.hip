@@ -85,6 +85,13 @@ struct fdw_ctx {
     int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0, timing = 0;
     int C = 4;  // columns per lane of the streaming kernels
     int adjK = 2, adjC = 2;  // time block and columns per lane of the reverse sweep
+    int adjS_cfg = 0;        // rows per reverse work item (0 = automatic)
+    // checkpoints of the adjoint stored by the forward run of one member (member < 0: off)
+    struct {
+        int member = -1;
+        int ck = 0;
+        void* ws = nullptr;
+    } rec;
     std::vector<hipEvent_t> ev_pool;  // instrumentation: start/end pairs of stencil launches
     size_t ev_used = 0;
     int S_eff = 0;
@@ -172,21 +179,22 @@ void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int
 int choose_K(const fdw_ctx* c)
 {
     if (c->K_cfg > 0) return c->K_cfg;
-    return c->dtype == FDW_F32 ? 4 : 2;
+    // deepest time block that keeps three waves per SIMD (2 columns per lane)
+    return c->dtype == FDW_F32 ? (c->C == 4 ? 6 : 8) : 4;
 }
 
 int choose_S(const fdw_ctx* c)
 {
     if (c->S_cfg > 0) return c->S_cfg;
-    // Aim at about 2048 streaming waves (2 per SIMD) for the largest member, with segments
-    // of at least 64 rows so that the 2K-row pipeline fill stays a small fraction.
-    int best = 64;
+    // Many short work items: aim at about 8192 streaming waves (several rounds of the 3072
+    // wave slots) for the largest member, with segments of 16 to 64 rows; a longer segment
+    // saves little of the 2K-row pipeline fill and leaves the chip with too few waves.
+    int best = kMinSegRows;
     for (const HostMember& hm : c->m) {
-        const int strips = max_strips(hm.nx);
-        int64_t want = ((int64_t)hm.ny * strips + 2047) / 2048;
-        int S = (int)std::max<int64_t>(64, want);
-        S = (S + 7) / 8 * 8;
-        best = std::max(best, std::min(S, (int)align_up((size_t)hm.ny, 8)));
+        const int64_t strips = max_strips(hm.nx);
+        int64_t S = (hm.ny * strips + 8191) / 8192;
+        S = std::min<int64_t>(64, std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8));
+        best = std::max(best, (int)S);
     }
     return best;
 }
@@ -228,6 +236,122 @@ void sync_member_dev(fdw_ctx* c, int i)
     md.traces = hm.traces;
 }
 
+struct AdjLayout {
+    size_t plane = 0, plane64 = 0;
+    int64_t nck = 0;
+    size_t total = 0;
+};
+
+AdjLayout adj_layout(const fdw_ctx* c, const HostMember& hm, int ck)
+{
+    AdjLayout L;
+    L.plane = align_up(plane_alloc(hm.ld, hm.ny, elem_size(c->dtype)), kAlign);
+    L.plane64 = align_up((size_t)hm.ld * hm.ny * sizeof(double), kAlign);
+    L.nck = (hm.N >= 1 && ck >= 1) ? (hm.N - 1) / ck : 0;  // checkpoints at ck, 2ck, ... < N
+    size_t b = align_up(sizeof(MemberDev), kAlign);
+    b += 8 * L.plane + 2 * L.plane64;
+    b += (size_t)(2 * L.nck) * L.plane;
+    b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);
+    b += align_up(sizeof(int) * (size_t)(hm.ny + 1), kAlign);
+    b += 2 * align_up(sizeof(int) * kMaxReceivers, kAlign);
+    b += align_up(sizeof(int) * 16, kAlign);
+    L.total = b;
+    return L;
+}
+
+
+// Adjoint workspace: a MemberDev slot, the reverse state planes (u, du, lam, mu; two of each),
+// two FP64 gradient planes, the checkpoints (u, du) at steps ck, 2ck, ... < N, and the
+// receiver tables.
+struct AdjPlanes {
+    MemberDev* rep_dev = nullptr;
+    void* planes_begin = nullptr;
+    void* FU[2];
+    void* FD[2];
+    void* LA[2];
+    void* MU[2];
+    double* G1 = nullptr;
+    double* G2 = nullptr;
+    std::vector<void*> CU, CD;
+    int* rec = nullptr;
+    int* rowptr = nullptr;
+    int* rcol = nullptr;
+    int* rid = nullptr;
+    int* status = nullptr;
+};
+
+AdjPlanes adj_carve(const fdw_ctx* c, const HostMember& hm, const AdjLayout& L, void* ws)
+{
+    AdjPlanes P;
+    char* w = (char*)ws;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = w + off;
+        off += align_up(bytes, kAlign);
+        return (void*)p;
+    };
+    const size_t es = elem_size(c->dtype);
+    P.rep_dev = (MemberDev*)take(sizeof(MemberDev));
+    P.planes_begin = w + off;
+    auto plane = [&]() { return plane_origin(take(L.plane), hm.ld, es); };
+    for (int k = 0; k < 2; ++k) P.FU[k] = plane();
+    for (int k = 0; k < 2; ++k) P.FD[k] = plane();
+    for (int k = 0; k < 2; ++k) P.LA[k] = plane();
+    for (int k = 0; k < 2; ++k) P.MU[k] = plane();
+    P.G1 = (double*)take(L.plane64);
+    P.G2 = (double*)take(L.plane64);
+    P.CU.resize(L.nck);
+    P.CD.resize(L.nck);
+    for (int64_t k = 0; k < L.nck; ++k) {
+        P.CU[k] = plane();
+        P.CD[k] = plane();
+    }
+    P.rec = (int*)take(sizeof(int) * 2 * kMaxReceivers);
+    P.rowptr = (int*)take(sizeof(int) * (size_t)(hm.ny + 1));
+    P.rcol = (int*)take(sizeof(int) * kMaxReceivers);
+    P.rid = (int*)take(sizeof(int) * kMaxReceivers);
+    P.status = (int*)take(sizeof(int) * 16);
+    return P;
+}
+
+// Copy the state (u^n, du^n) of a member into checkpoint slot n / ck - 1.
+int store_checkpoint(fdw_ctx* c, const HostMember& hm, void* cu, void* cd, const void* u, const void* d,
+                     hipStream_t s)
+{
+    const size_t es = elem_size(c->dtype);
+    const size_t pad = (size_t)kPadRowsTop * hm.ld * es;
+    const size_t bytes = plane_alloc(hm.ld, hm.ny, es);
+    HIPCHK(c, hipMemcpyAsync((char*)cu - pad, (const char*)u - pad, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync((char*)cd - pad, (const char*)d - pad, bytes, hipMemcpyDeviceToDevice, s));
+    return FDW_OK;
+}
+
+// Forward-run hook: when the recorded member has just reached a checkpoint step, store it.
+int record_hook(fdw_ctx* c, hipStream_t s)
+{
+    if (c->rec.member < 0) return FDW_OK;
+    const HostMember& hm = c->m[c->rec.member];
+    const int ck = c->rec.ck;
+    if (hm.n < 1 || hm.n % ck != 0 || hm.n >= hm.N) return FDW_OK;
+    const AdjLayout L = adj_layout(c, hm, ck);
+    const int64_t k = hm.n / ck - 1;
+    if (k >= L.nck) return FDW_OK;
+    // slot addresses follow the workspace layout of the adjoint
+    const size_t es = elem_size(c->dtype);
+    char* base = (char*)c->rec.ws + align_up(sizeof(MemberDev), kAlign) + 8 * L.plane + 2 * L.plane64;
+    void* cu = plane_origin(base + (size_t)(2 * k) * L.plane, hm.ld, es);
+    void* cd = plane_origin(base + (size_t)(2 * k + 1) * L.plane, hm.ld, es);
+    return store_checkpoint(c, hm, cu, cd, hm.u[hm.cur], hm.d[hm.cur], s);
+}
+
+// Steps until the recorded member's next checkpoint (a time block must not cross it).
+int64_t steps_to_checkpoint(const fdw_ctx* c)
+{
+    if (c->rec.member < 0) return INT64_MAX;
+    const int64_t n = c->m[c->rec.member].n;
+    return c->rec.ck - (n % c->rec.ck);
+}
+
 template <typename T>
 int do_start(fdw_ctx* c, int i, double* energy_out)
 {
@@ -240,7 +364,7 @@ int do_start(fdw_ctx* c, int i, double* energy_out)
     if (hm.R > 0 && hm.traces && 1 < hm.N + 1)
         HIPCHK(c, launch_gather<T>(hm.u[0], hm.ld, hm.rec_ij, hm.R, (char*)hm.traces + (size_t)hm.R * sizeof(T),
                                    c->stream));
-    return FDW_OK;
+    return record_hook(c, c->stream);
 }
 
 // One streaming launch of K steps over members [first, first + nm) (all members when nm == count).
@@ -307,7 +431,7 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
     int64_t left = steps, k = koff;
     int curK = -1;
     while (left > 0) {
-        const int Kb = (int)std::min<int64_t>(K, left);
+        const int Kb = (int)std::min<int64_t>(std::min<int64_t>(K, left), steps_to_checkpoint(c));
         if (Kb != curK) {
             int rc = layout_for_K(c, Kb, c->S_eff, s);
             if (rc) return rc;
@@ -323,6 +447,8 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
             hm.n += Kb;
             hm.cur ^= 1;
         }
+        rc = record_hook(c, s);
+        if (rc) return rc;
         left -= Kb;
         k += Kb;
     }
@@ -413,8 +539,9 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
     }
     const int64_t left = n - done;
     if (left <= 0) return FDW_OK;
-    if (c->batch_mode == 1 && energy_dev == nullptr && !any_trace(c)) return run_persistent<T>(c, left);
-    if (c->use_graph && !any_trace(c)) {
+    const bool recording = c->rec.member >= 0;
+    if (c->batch_mode == 1 && energy_dev == nullptr && !any_trace(c) && !recording) return run_persistent<T>(c, left);
+    if (c->use_graph && !any_trace(c) && !recording) {
         // The launch sequence of the main loop depends only on (steps, K, energy pointer and
         // offset, launch parity); capture it once and replay it.
         const auto key = std::make_tuple(left, choose_K(c), (const double*)energy_dev, (int)(c->launches & 1),
@@ -512,7 +639,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
     c->dtype = problems[0].dtype;
     c->C = default_cols_per_lane(c->dtype);
     c->adjC = (c->dtype == FDW_F64) ? 1 : 2;
-    c->adjK = 2;
+    c->adjK = 4;
     c->stream = (hipStream_t)hip_stream;
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
@@ -664,6 +791,7 @@ int fdw_set_coeff(fdw_ctx* c, int32_t m, const void* h1, const void* h2)
     hm.coeff = true;
     hm.n = 0;
     hm.cur = 0;
+    if (c->rec.member == m) c->rec.member = -1;
     sync_member_dev(c, m);
     invalidate_graphs(c);
     return push_member(c, m);
@@ -781,6 +909,7 @@ int fdw_set_state(fdw_ctx* c, int32_t m, const void* u, const void* du, int64_t 
     HIPCHK(c, (c->dtype == FDW_F32) ? launch_copy_in<float>(du, hm.nx, hm.ny, hm.d[hm.cur], hm.ld, 1, c->stream)
                                     : launch_copy_in<double>(du, hm.nx, hm.ny, hm.d[hm.cur], hm.ld, 1, c->stream));
     hm.n = n;
+    if (c->rec.member == m) c->rec.member = -1;
     sync_member_dev(c, m);
     invalidate_graphs(c);
     return push_member(c, m);
@@ -816,6 +945,7 @@ int fdw_reset(fdw_ctx* c, int32_t m)
     if (rc) return rc;
     c->m[m].n = 0;
     c->m[m].cur = 0;
+    if (c->rec.member == m) c->rec.member = -1;
     sync_member_dev(c, m);
     invalidate_graphs(c);
     return push_member(c, m);
@@ -862,7 +992,7 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         c->C = (int)v;
         break;
     case FDW_CFG_ADJ_TIME_BLOCK:
-        if (v == 0) v = 2;
+        if (v == 0) v = 4;
         if (v < 1 || v > 4) return fail(c, FDW_EINVAL, "adjoint time block must be 1..4");
         c->adjK = (int)v;
         break;
@@ -871,6 +1001,10 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         if (!(v == 2 || (v == 4 && c->dtype == FDW_F32) || (v == 1 && c->dtype == FDW_F64)))
             return fail(c, FDW_EINVAL, "adjoint lane columns must be 2 or 4 (float) / 1 or 2 (double)");
         c->adjC = (int)v;
+        break;
+    case FDW_CFG_ADJ_SEGMENT_ROWS:
+        if (v != 0 && (v < kMinSegRows || v > 4096)) return fail(c, FDW_EINVAL, "segment rows must be 0 or 16..4096");
+        c->adjS_cfg = (int)v;
         break;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
@@ -907,6 +1041,7 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
     case FDW_CFG_LANE_COLUMNS: return c->C;
     case FDW_CFG_ADJ_TIME_BLOCK: return c->adjK;
     case FDW_CFG_ADJ_LANE_COLUMNS: return c->adjC;
+    case FDW_CFG_ADJ_SEGMENT_ROWS: return c->adjS_cfg;
     default: return -1;
     }
 }
@@ -920,27 +1055,17 @@ namespace {
 
 int adjoint_K(const fdw_ctx* c) { return c->adjK; }
 
-struct AdjLayout {
-    size_t plane = 0, plane64 = 0;
-    int64_t nck = 0;
-    size_t total = 0;
-};
-
-AdjLayout adj_layout(const fdw_ctx* c, const HostMember& hm, int ck)
+// Rows per reverse work item: the reverse kernel holds about twice the registers of the
+// forward one (two waves per SIMD); aim at 8192 waves, with segments of at least 16 rows.
+int choose_adj_S(const fdw_ctx* c, const HostMember& hm)
 {
-    AdjLayout L;
-    L.plane = align_up(plane_alloc(hm.ld, hm.ny, elem_size(c->dtype)), kAlign);
-    L.plane64 = align_up((size_t)hm.ld * hm.ny * sizeof(double), kAlign);
-    L.nck = (hm.N >= 1 && ck >= 1) ? (hm.N - 1) / ck : 0;  // checkpoints at ck, 2ck, ... < N
-    size_t b = align_up(sizeof(MemberDev), kAlign);
-    b += 8 * L.plane + 2 * L.plane64;
-    b += (size_t)(2 * L.nck) * L.plane;
-    b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);
-    b += align_up(sizeof(int) * (size_t)(hm.ny + 1), kAlign);
-    b += 2 * align_up(sizeof(int) * kMaxReceivers, kAlign);
-    b += align_up(sizeof(int) * 16, kAlign);
-    L.total = b;
-    return L;
+    if (c->adjS_cfg > 0) return c->adjS_cfg;
+    const int Hx = ((c->adjK + c->adjC - 1) / c->adjC) * c->adjC;
+    const int Wv = kWaveSize * c->adjC - 2 * Hx;
+    const int64_t strips = (hm.nx + Wv - 1) / Wv;
+    int64_t S = (hm.ny * strips + 8191) / 8192;
+    S = std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8);
+    return (int)std::min<int64_t>(S, std::max<int64_t>(kMinSegRows, align_up((size_t)hm.ny, 8)));
 }
 
 void adj_decompose(const fdw_ctx* c, const HostMember& hm, int K, int S, AdjArgs& a)
@@ -961,41 +1086,29 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     HostMember& hm = c->m[m];
     const AdjLayout L = adj_layout(c, hm, ck);
     if (wsb < L.total) return fail(c, FDW_ENOMEM, "adjoint workspace too small");
-    char* w = (char*)ws;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        char* p = w + off;
-        off += align_up(bytes, kAlign);
-        return (void*)p;
-    };
-    MemberDev* rep_dev = (MemberDev*)take(sizeof(MemberDev));
-    void* FU[2];
-    void* FD[2];
-    void* LA[2];
-    void* MU[2];
-    const size_t es = elem_size(c->dtype);
-    void* planes_begin = w + off;
-    auto plane = [&]() { return plane_origin(take(L.plane), hm.ld, es); };
-    for (int k = 0; k < 2; ++k) FU[k] = plane();
-    for (int k = 0; k < 2; ++k) FD[k] = plane();
-    for (int k = 0; k < 2; ++k) LA[k] = plane();
-    for (int k = 0; k < 2; ++k) MU[k] = plane();
-    double* G1 = (double*)take(L.plane64);
-    double* G2 = (double*)take(L.plane64);
-    std::vector<void*> CU(L.nck), CD(L.nck);
-    for (int64_t k = 0; k < L.nck; ++k) {
-        CU[k] = plane();
-        CD[k] = plane();
-    }
-    int* rec = (int*)take(sizeof(int) * 2 * kMaxReceivers);
-    int* rowptr = (int*)take(sizeof(int) * (size_t)(hm.ny + 1));
-    int* rcol = (int*)take(sizeof(int) * kMaxReceivers);
-    int* rid = (int*)take(sizeof(int) * kMaxReceivers);
-    int* status = (int*)take(sizeof(int) * 16);
+    const AdjPlanes P = adj_carve(c, hm, L, ws);
+    void* const* FU = P.FU;
+    void* const* FD = P.FD;
+    void* const* LA = P.LA;
+    void* const* MU = P.MU;
+    double* G1 = P.G1;
+    double* G2 = P.G2;
+    const std::vector<void*>& CU = P.CU;
+    const std::vector<void*>& CD = P.CD;
+    int* rec = P.rec;
+    int* rowptr = P.rowptr;
+    int* rcol = P.rcol;
+    int* rid = P.rid;
+    int* status = P.status;
+    MemberDev* rep_dev = P.rep_dev;
     hipStream_t s = c->stream;
+    const int64_t N = hm.N;
+    // The forward run of this member stored every checkpoint into this workspace and stopped
+    // at step N: reverse from its final state without a replay.
+    const bool recorded = c->rec.member == m && c->rec.ws == ws && c->rec.ck == ck && hm.n == N && N >= 1;
 
-    // zero the state planes (boundary ring and padding must be 0) and the accumulators
-    HIPCHK(c, launch_fill_bytes(planes_begin, 8 * L.plane + 2 * L.plane64, s));
+    // zero the reverse state planes (boundary ring and padding must be 0) and the accumulators
+    HIPCHK(c, launch_fill_bytes(P.planes_begin, 8 * L.plane + 2 * L.plane64, s));
     if (R > 0) {
         HIPCHK(c, hipMemcpyAsync(rec, recv_ij, sizeof(int) * 2 * (size_t)R, hipMemcpyDeviceToDevice, s));
         HIPCHK(c, launch_receivers_csr(rec, R, hm.nx, hm.ny, rowptr, rcol, rid, status, s));
@@ -1004,67 +1117,71 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
         HIPCHK(c, hipStreamSynchronize(s));
         if (st != 0) return fail(c, FDW_EINVAL, "receivers must be interior nodes (1 <= i <= nx-2, 1 <= j <= ny-2)");
     }
-    const int64_t N = hm.N;
     if (N == 0) {
         HIPCHK(c, launch_grad_out(G1, hm.ld, hm.nx, hm.ny, g1_out, s));
         if (g2_out) HIPCHK(c, launch_grad_out(G2, hm.ld, hm.nx, hm.ny, g2_out, s));
         return FDW_OK;
     }
 
-    // ---- forward replay from the initial data, storing (u, du) every ck steps
     MemberDev rep = c->tab[m];
-    for (int k = 0; k < 2; ++k) {
-        rep.u[k] = FU[k];
-        rep.d[k] = FD[k];
-    }
-    rep.R = 0;
-    rep.traces = nullptr;
-    rep.cur0 = 0;
-    rep.n_offset = 0;
-    rep.block_base = 0;
-    HIPCHK(c, launch_start<T>(&rep, rep_dev, hm.u0, hm.u1, (T)hm.tau, 0, 0, nullptr, c->red, s));
     int cur = 0;
-    int64_t n = 1;
-    const int Kf = choose_K(c);
-    int pushedK = -1;
-    auto store_ckpt = [&](int64_t step) -> int {
-        const int64_t k = step / ck - 1;
-        const size_t pad = (size_t)kPadRowsTop * hm.ld * es;
-        const size_t bytes = plane_alloc(hm.ld, hm.ny, es);
-        HIPCHK(c, hipMemcpyAsync((char*)CU[k] - pad, (char*)FU[cur] - pad, bytes, hipMemcpyDeviceToDevice, s));
-        HIPCHK(c, hipMemcpyAsync((char*)CD[k] - pad, (char*)FD[cur] - pad, bytes, hipMemcpyDeviceToDevice, s));
-        return FDW_OK;
-    };
-    if (n % ck == 0 && n < N) {
-        int rc = store_ckpt(n);
-        if (rc) return rc;
-    }
-    while (n < N) {
-        const int64_t next = std::min<int64_t>(N, (n / ck + 1) * ck);
-        const int Kb = (int)std::min<int64_t>(Kf, next - n);
-        if (Kb != pushedK) {
-            decompose(c, hm, rep, c->S_eff, Kb);
-            hipLaunchKernelGGL(k_write_member, dim3(1), dim3(1), 0, s, rep_dev, 0, rep);
-            HIPCHK(c, hipGetLastError());
-            pushedK = Kb;
+    const void* top_u = nullptr;
+    const void* top_d = nullptr;
+    if (recorded) {
+        top_u = hm.u[hm.cur];
+        top_d = hm.d[hm.cur];
+    } else {
+        // ---- forward replay from the initial data, storing (u, du) every ck steps
+        for (int k = 0; k < 2; ++k) {
+            rep.u[k] = FU[k];
+            rep.d[k] = FD[k];
         }
-        StepArgs a;
-        a.table = rep_dev;
-        a.first = 0;
-        a.nmembers = 1;
-        a.block_offset = 0;
-        a.total_blocks = rep.blocks;
-        a.parity = cur;
-        a.want_energy = 0;
-        a.want_trace = 0;
-        a.ctx_step = 0;
-        HIPCHK(c, launch_step<T>(a, Kb, c->C, hm.face, rep.blocks, s));
-        cur ^= 1;
-        n += Kb;
+        rep.R = 0;
+        rep.traces = nullptr;
+        rep.cur0 = 0;
+        rep.n_offset = 0;
+        rep.block_base = 0;
+        HIPCHK(c, launch_start<T>(&rep, rep_dev, hm.u0, hm.u1, (T)hm.tau, 0, 0, nullptr, c->red, s));
+        int64_t n = 1;
+        const int Kf = choose_K(c);
+        int pushedK = -1;
+        auto store_ckpt = [&](int64_t step) -> int {
+            const int64_t k = step / ck - 1;
+            return store_checkpoint(c, hm, CU[k], CD[k], FU[cur], FD[cur], s);
+        };
         if (n % ck == 0 && n < N) {
             int rc = store_ckpt(n);
             if (rc) return rc;
         }
+        while (n < N) {
+            const int64_t next = std::min<int64_t>(N, (n / ck + 1) * ck);
+            const int Kb = (int)std::min<int64_t>(Kf, next - n);
+            if (Kb != pushedK) {
+                decompose(c, hm, rep, c->S_eff, Kb);
+                hipLaunchKernelGGL(k_write_member, dim3(1), dim3(1), 0, s, rep_dev, 0, rep);
+                HIPCHK(c, hipGetLastError());
+                pushedK = Kb;
+            }
+            StepArgs a;
+            a.table = rep_dev;
+            a.first = 0;
+            a.nmembers = 1;
+            a.block_offset = 0;
+            a.total_blocks = rep.blocks;
+            a.parity = cur;
+            a.want_energy = 0;
+            a.want_trace = 0;
+            a.ctx_step = 0;
+            HIPCHK(c, launch_step<T>(a, Kb, c->C, hm.face, rep.blocks, s));
+            cur ^= 1;
+            n += Kb;
+            if (n % ck == 0 && n < N) {
+                int rc = store_ckpt(n);
+                if (rc) return rc;
+            }
+        }
+        top_u = FU[cur];
+        top_d = FD[cur];
     }
 
     // ---- reverse sweep
@@ -1090,11 +1207,12 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     A.rec_rowptr = rowptr;
     A.rec_col = rcol;
     A.rec_id = rid;
-    const void* fu_in = FU[cur];
-    const void* fd_in = FD[cur];
-    int fcur = cur;
+    const void* fu_in = top_u;
+    const void* fd_in = top_d;
+    int fcur = recorded ? 1 : cur;  // the first reverse output goes to the other state plane
     int lcur = 0;
     const int Kr = adjoint_K(c);
+    const int Sr = choose_adj_S(c, hm);
     int64_t mtop = N;
     while (mtop > 0) {
         if (mtop < N && mtop % ck == 0) {
@@ -1105,7 +1223,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
         }
         const int64_t seg_bot = ((mtop - 1) / ck) * ck;
         const int Kb = (int)std::min<int64_t>(Kr, mtop - seg_bot);
-        adj_decompose(c, hm, Kb, c->S_eff, A);
+        adj_decompose(c, hm, Kb, Sr, A);
         const int outk = fcur ^ 1;
         A.uin = fu_in;
         A.din = fd_in;
@@ -1137,6 +1255,26 @@ size_t fdw_adjoint_workspace_bytes(const fdw_ctx* c, int32_t m, int32_t ckpt_eve
 {
     if (!c || m < 0 || m >= c->count || ckpt_every < 1) return 0;
     return adj_layout(c, c->m[m], ckpt_every).total;
+}
+
+int fdw_record_checkpoints(fdw_ctx* c, int32_t m, int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    if (!adj_ws) {
+        if (c->rec.member == m) c->rec.member = -1;
+        return FDW_OK;
+    }
+    HostMember& hm = c->m[m];
+    if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
+    if (hm.n != 0) return fail(c, FDW_ESTATE, "checkpoint recording starts at step 0 (fdw_reset or fdw_set_coeff first)");
+    if (ckpt_every < 1) return fail(c, FDW_EINVAL, "ckpt_every must be >= 1");
+    if (((uintptr_t)adj_ws) % kAlign) return fail(c, FDW_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (adj_ws_bytes < adj_layout(c, hm, ckpt_every).total) return fail(c, FDW_ENOMEM, "adjoint workspace too small");
+    c->rec.member = m;
+    c->rec.ck = ckpt_every;
+    c->rec.ws = adj_ws;
+    return FDW_OK;
 }
 
 int fdw_adjoint(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, const double* trace_grad, int32_t ckpt_every,
@@ -1238,7 +1376,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         } else {
             for (int K = 1; K <= 4; ++K) CK.push_back({2, K});
         }
-        const int Ss[] = {32, 64, 128, 256, 512};
+        const int Ss[] = {16, 32, 64, 128};
         const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode, saveC = c->C;
         c->use_graph = 0;
         c->batch_mode = 0;

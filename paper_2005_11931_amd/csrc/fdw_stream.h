@@ -109,6 +109,21 @@ struct Lanes<double> {
     static constexpr int C = 2;
 };
 
+// Pointer into the constant address space, for tables a kernel only reads (receiver lists):
+// wave-uniform loads through it become scalar loads, which complete on their own counter
+// instead of waiting behind the outstanding vector loads of the row prefetch.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar) value.  Written as
+// threadIdx.x / 64 it is a per-lane value to the compiler, and everything derived from it
+// (work item, row range, buffer descriptors) would live in vector registers, with every
+// buffer load wrapped in a loop over the distinct descriptors of the lanes.
+__device__ __forceinline__ int wave_in_block()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give each
@@ -178,14 +193,12 @@ __device__ __forceinline__ void buffer_row(__amdgpu_buffer_rsrc_t r, unsigned in
     for (int c = 0; c < C; ++c) out[c] = q.v[c];
 }
 
-// MODE 0: plain steps; 1: per-step energy (traces recorded when `trace` is set); 2: traces only.
-// (The energy variants keep the trace path compiled in: without it the register allocator
-// of this toolchain produces a much larger footprint for some time blocks.)
+// MODE bit 0: per-step energy partials; bit 1: receiver traces.
 template <typename T, int K, int C, int FACE, int MODE>
-__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step, int trace)
+__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step)
 {
-    constexpr bool want_energy = MODE == 1;
-    const bool want_trace = (MODE == 2) || (MODE == 1 && trace != 0);
+    constexpr bool want_energy = (MODE & 1) != 0;
+    constexpr bool want_trace = (MODE & 2) != 0;
     constexpr int Hx = ((K + C - 1) / C) * C;   // halo columns on each side (multiple of C)
     constexpr int Wv = kWaveSize * C - 2 * Hx;  // owned columns per strip
     constexpr int U = RowUnroll<K>::U;
@@ -352,18 +365,26 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
                         ps = fma_t(-nu[c], L[c], ps);
                     }
                     eb[t - 1] += ps;
+                    // an empty asm that reads and writes the partial sum pins this addition
+                    // here: otherwise the compiler defers the energy arithmetic of the whole
+                    // unrolled block to its end, keeping every level's nu, nd and L of every
+                    // row alive (several hundred registers at K >= 3)
+                    asm volatile("" : "+v"(eb[t - 1]));
                 }
                 if (want_trace && rown && rin) {
-                    const int kb = M.rec_rowptr[r], ke = M.rec_rowptr[r + 1];
+                    const ConstPtr<int> rowptr = (ConstPtr<int>)M.rec_rowptr;
+                    const ConstPtr<int> rcol = (ConstPtr<int>)M.rec_col;
+                    const ConstPtr<int> rid = (ConstPtr<int>)M.rec_id;
+                    const int kb = rowptr[r], ke = rowptr[r + 1];
                     const int64_t row = n0 + t;
                     if (kb < ke && row < M.trace_rows) {
                         for (int k = kb; k < ke; ++k) {
-                            const int off = M.rec_col[k] - cb;
+                            const int off = rcol[k] - cb;
                             if (lane_owned && off >= 0 && off < C) {
                                 T v = nu[0];
 #pragma unroll
                                 for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
-                                ((T*)M.traces)[row * M.R + M.rec_id[k]] = v;
+                                ((T*)M.traces)[row * M.R + rid[k]] = v;
                             }
                         }
                     }
@@ -412,16 +433,18 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step(StepArgs a)
     const int gb = xcd_remap(blockIdx.x, a.total_blocks) + a.block_offset;
     const int m = find_member(a.table, a.first, a.nmembers, gb);
     const MemberDev& M = a.table[m];
-    const int wave = (gb - M.block_base) * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wave = (gb - M.block_base) * kWavesPerBlock + wave_in_block();
     if (wave >= M.waves) return;
-    sweep_item<T, K, C, FACE, MODE>(M, wave, a.parity, a.ctx_step, a.want_trace);
+    sweep_item<T, K, C, FACE, MODE>(M, wave, a.parity, a.ctx_step);
 }
 
 template <typename T, int K, int C, int FACE>
 static hipError_t launch_step_kcf(const StepArgs& a, int grid, hipStream_t s)
 {
     const dim3 g(grid), b(kWaveSize * kWavesPerBlock);
-    if (a.want_energy)
+    if (a.want_energy && a.want_trace)
+        hipLaunchKernelGGL((k_step<T, K, C, FACE, 3>), g, b, 0, s, a);
+    else if (a.want_energy)
         hipLaunchKernelGGL((k_step<T, K, C, FACE, 1>), g, b, 0, s, a);
     else if (a.want_trace)
         hipLaunchKernelGGL((k_step<T, K, C, FACE, 2>), g, b, 0, s, a);
@@ -490,7 +513,7 @@ template <typename T, int K, int C, int FACE>
 __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar)
 {
     const int total_waves = a.total_blocks * kWavesPerBlock;  // work items of one time block
-    const int gw0 = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int gw0 = blockIdx.x * kWavesPerBlock + wave_in_block();
     const int stride = gridDim.x * kWavesPerBlock;
     int gen = 0;
     int parity = a.parity;
@@ -501,7 +524,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(
             const int m = find_member(a.table, a.first, a.nmembers, gb);
             const MemberDev& M = a.table[m];
             const int wave = (gb - M.block_base) * kWavesPerBlock + (item % kWavesPerBlock);
-            if (wave < M.waves) sweep_item<T, K, C, FACE, 0>(M, wave, parity, step, 0);
+            if (wave < M.waves) sweep_item<T, K, C, FACE, 0>(M, wave, parity, step);
         }
         parity ^= 1;
         step += K;

@@ -28,11 +28,11 @@ FDW_F32, FDW_F64 = 0, 1
 FDW_OK, FDW_EINVAL, FDW_ECFL, FDW_ESTATE, FDW_ENOMEM, FDW_EHIP, FDW_EUNSTABLE, FDW_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 FDW_ALLOW_UNSTABLE, FDW_ALLOW_ZERO_H = 1, 2
 FDW_CFG_TIME_BLOCK, FDW_CFG_SEGMENT_ROWS, FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE, FDW_CFG_TIMING = 1, 2, 3, 4, 5
-FDW_CFG_LANE_COLUMNS, FDW_CFG_ADJ_TIME_BLOCK, FDW_CFG_ADJ_LANE_COLUMNS = 6, 7, 8
+FDW_CFG_LANE_COLUMNS, FDW_CFG_ADJ_TIME_BLOCK, FDW_CFG_ADJ_LANE_COLUMNS, FDW_CFG_ADJ_SEGMENT_ROWS = 6, 7, 8, 9
 
 EXPORTED = [
     "fdw_workspace_bytes", "fdw_init", "fdw_set_coeff", "fdw_step_n", "fdw_energy", "fdw_record_traces",
-    "fdw_misfit", "fdw_adjoint_workspace_bytes", "fdw_adjoint", "fdw_get_state", "fdw_set_state", "fdw_reset",
+    "fdw_misfit", "fdw_adjoint_workspace_bytes", "fdw_record_checkpoints", "fdw_adjoint", "fdw_get_state", "fdw_set_state", "fdw_reset",
     "fdw_member_distance",
     "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_kernel_time", "fdw_last_error",
     "fdw_status_string", "fdw_destroy",
@@ -60,6 +60,8 @@ _lib.fdw_energy.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
 _lib.fdw_record_traces.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp]
 _lib.fdw_misfit.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp]
 _lib.fdw_adjoint_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+_lib.fdw_record_checkpoints.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t]
+_lib.fdw_record_checkpoints.restype = ctypes.c_int
 _lib.fdw_adjoint_workspace_bytes.restype = ctypes.c_size_t
 _lib.fdw_adjoint.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_size_t,
                              _vp, _vp]
@@ -151,6 +153,7 @@ class Solver:
         self.ctx = ctx
         self._h = [None] * self.count
         self._traces = [None] * self.count
+        self._ckpt = None  # (member, ckpt_every, workspace) of an armed checkpoint recording
 
     # -- helpers
     def _check(self, st: int):
@@ -213,15 +216,34 @@ class Solver:
                                     _ptr(J), _ptr(g)))
         return J, g
 
+    def _adjoint_workspace(self, member: int, ckpt_every: int) -> torch.Tensor:
+        nb = _lib.fdw_adjoint_workspace_bytes(self.ctx, member, ckpt_every)
+        if nb == 0:
+            raise FdwError(FDW_EINVAL, "fdw_adjoint_workspace_bytes failed")
+        return torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    def record_checkpoints(self, ckpt_every: Optional[int] = 64, member: int = 0):
+        """Store the adjoint's checkpoints during the coming forward run of `member` (which must
+        be at step 0), so that `adjoint` with the same ckpt_every skips its replay.
+        ckpt_every=None stops the recording."""
+        if ckpt_every is None:
+            self._check(_lib.fdw_record_checkpoints(self.ctx, member, 1, None, 0))
+            self._ckpt = None
+            return
+        ws = self._adjoint_workspace(member, ckpt_every)
+        self._check(_lib.fdw_record_checkpoints(self.ctx, member, ckpt_every, _ptr(ws), ws.numel()))
+        self._ckpt = (member, ckpt_every, ws)
+
     def adjoint(self, receivers: torch.Tensor, trace_grad: torch.Tensor, ckpt_every: int = 64, member: int = 0,
                 separate: bool = False):
         p = self.problems[member]
         rec = receivers.to(device=self.device, dtype=torch.int32).contiguous()
         tg = trace_grad.to(device=self.device, dtype=torch.float64).contiguous()
-        nb = _lib.fdw_adjoint_workspace_bytes(self.ctx, member, ckpt_every)
-        if nb == 0:
-            raise FdwError(FDW_EINVAL, "fdw_adjoint_workspace_bytes failed")
-        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        if self._ckpt is not None and self._ckpt[0] == member and self._ckpt[1] == ckpt_every:
+            ws = self._ckpt[2]  # the library checks whether the recording is complete
+        else:
+            ws = self._adjoint_workspace(member, ckpt_every)
+        nb = ws.numel()
         g1 = torch.empty((p.ny, p.nx), dtype=torch.float64, device=self.device)
         g2 = torch.empty((p.ny, p.nx), dtype=torch.float64, device=self.device) if separate else None
         self._check(_lib.fdw_adjoint(self.ctx, member, _ptr(rec), rec.shape[0], _ptr(tg), ckpt_every, _ptr(ws), nb,
@@ -301,8 +323,10 @@ def family_solver(cases, dtype: int = FDW_F32, device: str = "cuda:0") -> Solver
 class FdwMisfit(torch.autograd.Function):
     """loss = sum_{n,r} (u^n(receiver r) - d_{n,r})^2 as a function of the nodal depth h (h1 = h2 = h).
 
-    forward: set the coefficient, run the leapfrog solve recording traces, FP64 misfit (libfdw).
-    backward: adjoint source 2 (traces - d) * grad_output, reverse leapfrog (libfdw) -> dL/dh.
+    forward: set the coefficient, run the leapfrog solve recording traces and the adjoint's
+    checkpoints, FP64 misfit (libfdw).
+    backward: adjoint source 2 (traces - d) * grad_output, reverse leapfrog from the recorded
+    checkpoints (libfdw) -> dL/dh.
     """
 
     @staticmethod
@@ -311,6 +335,7 @@ class FdwMisfit(torch.autograd.Function):
         p = solver.problems[0]
         N = int(round(p.T / p.tau))
         solver.set_coeff(h.detach().to(solver.tdtype))
+        solver.record_checkpoints(ckpt_every)
         tr = solver.record_traces(receivers)
         solver.step(N)
         J, g = solver.misfit(tr, d_obs)

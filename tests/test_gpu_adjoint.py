@@ -209,3 +209,70 @@ def test_adjoint_workload_full_size_fd():
         _say("dir", k, fd, ad, abs(fd - ad) / abs(fd))
     assert worst <= 1e-6
     s.close()
+
+
+@pytest.mark.parametrize("ck", [1, 7, 64])
+def test_recorded_checkpoints_equal_replay(ck):
+    """Checkpoints stored by the forward run (with traces and energies on) give the same gradient,
+    bit for bit, as the adjoint's own replay; a new coefficient stops the recording and the
+    adjoint falls back to the replay."""
+    import torch
+
+    fdw = _fdw()
+    case, d = _problem(seed=21)
+    _say("recorded checkpoints ck", ck)
+    rec = torch.as_tensor(case.receivers)
+    ref = oracle.forward_case(case)
+    tg = torch.as_tensor(2.0 * (ref["traces"] - d))
+    s0 = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    g_replay = s0.adjoint(rec, tg, ckpt_every=ck).cpu().numpy()
+    s0.close()
+
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    s.record_checkpoints(ck)
+    tr = s.record_traces(rec)
+    s.step(case.nsteps, energy=True)
+    assert np.abs(tr.cpu().numpy() - ref["traces"]).max() <= 1e-12
+    g_rec = s.adjoint(rec, tg, ckpt_every=ck).cpu().numpy()
+    assert np.array_equal(g_rec, g_replay)
+    # the recording stays usable for a second trace gradient
+    g_rec2 = s.adjoint(rec, 2.0 * tg, ckpt_every=ck).cpu().numpy()
+    assert np.allclose(g_rec2, 2.0 * g_replay, rtol=1e-12, atol=0)
+    # new coefficient: recording off, the adjoint replays
+    h2 = case.h1 * 1.01
+    s.set_coeff(torch.as_tensor(h2, device="cuda"))
+    s.step(case.nsteps)
+    c2 = I.Case(**{**case.__dict__, "h1": h2})
+    g_new = s.adjoint(rec, tg, ckpt_every=ck).cpu().numpy()
+    gref = oracle.adjoint(c2.nx, c2.ny, c2.dx, c2.dy, c2.tau, c2.h1, None, c2.u0, c2.u1, c2.nsteps, c2.receivers,
+                          tg.numpy(), ckpt_every=ck)
+    assert np.linalg.norm(g_new - gref) <= 1e-9 * np.linalg.norm(gref)
+    s.close()
+
+
+def test_recorded_checkpoints_batched_member():
+    """Recording one member of a two-member context (the other member on another grid)."""
+    import torch
+
+    fdw = _fdw()
+    case_a, _ = _problem(nx=64, ny=72, N=120, seed=31)
+    case_b, d = _problem(nx=90, ny=70, N=120, seed=32)
+    # both members share tau and N; the gradient is for member 1
+    tau = min(case_a.tau, case_b.tau)
+    case_a = I.Case(**{**case_a.__dict__, "tau": tau})
+    case_b = I.Case(**{**case_b.__dict__, "tau": tau})
+    _say("recorded checkpoints, batched")
+    ps = [fdw.problem_from_case(c, fdw.FDW_F64) for c in (case_a, case_b)]
+    S = fdw.Solver(ps, [torch.as_tensor(c.u0, device="cuda") for c in (case_a, case_b)],
+                   [torch.as_tensor(c.u1, device="cuda") for c in (case_a, case_b)])
+    for m, c in enumerate((case_a, case_b)):
+        S.set_coeff(torch.as_tensor(c.h1, device="cuda"), member=m)
+    S.record_checkpoints(16, member=1)
+    S.step(case_b.nsteps)
+    ref = oracle.forward_case(case_b)
+    tg = 2.0 * (ref["traces"] - d)
+    g = S.adjoint(torch.as_tensor(case_b.receivers), torch.as_tensor(tg), ckpt_every=16, member=1).cpu().numpy()
+    gref = oracle.adjoint(case_b.nx, case_b.ny, case_b.dx, case_b.dy, case_b.tau, case_b.h1, None, case_b.u0,
+                          case_b.u1, case_b.nsteps, case_b.receivers, tg, ckpt_every=16)
+    assert np.linalg.norm(g - gref) <= 1e-9 * np.linalg.norm(gref)
+    S.close()

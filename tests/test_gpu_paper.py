@@ -59,7 +59,13 @@ def test_section_3_2_3_second_wave(kind):
     print("section 3.2.3", kind, "steps", case.nsteps, flush=True)
     u, _ = _gpu(case, flags=fdw.FDW_ALLOW_ZERO_H)
     ref = oracle.forward_case(case)["u_cur"]
-    assert np.abs(u - ref).max() <= 1e-12 * np.abs(case.u0).max()
+    # 12k-51k steps: the two sides round in a different order every step, and leapfrog neither
+    # damps nor amplifies those differences, so they add up at most linearly in N: a few
+    # roundings of the largest value per update and step
+    tol = 4.0 * case.nsteps * np.finfo(np.float64).eps * np.abs(case.u0).max()
+    err = np.abs(u - ref).max()
+    print("max abs", err, "bound", tol, flush=True)
+    assert err <= tol
     x = I.node_coords(case.nx, 0.0, 100.0)
     row = u[1]
     incident = np.abs(case.u0).max() / 2.0
