@@ -14,9 +14,9 @@ oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
        python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: one 400-step
-                        forward solve plus a 1 GiB device copy used to calibrate the counters)
-       python bench.py --summarize-profile DIR --out NAME (writes profiles/NAME.txt from the
-                        rocprofv3 stats/counter CSV files under DIR)
+                        forward solve plus three plain copies used to calibrate the counters)
+       python bench.py --summarize-profile DIR [DIR ...] --out NAME (writes profiles/NAME.txt,
+                        and NAME.json with calibrated bytes per launch, from rocprofv3 CSV files)
 """
 from __future__ import annotations
 
@@ -102,10 +102,13 @@ def forward_bench(fdw, torch, I, dtype, steps, warmup, n=8192, nsteps=5000):
                 n=n, nsteps=nsteps)
 
 
-def family_bench(fdw, torch, I, steps, warmup):
+def family_bench(fdw, torch, I, steps, warmup, persistent=False):
     fam = I.family()
     s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
-    s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+    if persistent:
+        s.configure(fdw.FDW_CFG_BATCH_MODE, 1)  # one cooperative launch per step call
+    else:
+        s.configure(fdw.FDW_CFG_USE_GRAPH, 1)  # one launch per time block over all members, in a graph
     nsteps = fam[0].nsteps
     updates = sum((c.nx - 2) * (c.ny - 2) * c.nsteps for c in fam)
     bytes_alg = sum(c.nx * c.ny for c in fam) * 5 * 4 * nsteps / s.config(fdw.FDW_CFG_TIME_BLOCK)
@@ -216,66 +219,84 @@ def cpu_baseline(I, budget_s=15.0):
 
 
 def profile_run(dtype_name: str):
-    """Short, profiler-friendly run: a 1 GiB device-to-device copy (torch's copy kernel, known
-    size, for counter calibration) and one 400-step forward solve of the 8192^2 workload."""
+    """Short, profiler-friendly run: one 400-step forward solve of the 8192^2 workload with
+    per-step energy (the configuration the bench times), then three state read-outs: each is a
+    plain copy kernel (k_copy_out) that reads and writes exactly n*n words, used to calibrate
+    the memory counters."""
     import torch
 
     from paper_2005_11931_amd import fdw
     from paper_2005_11931_amd import inputs as I
 
-    n_bytes = 1 << 30
-    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    log("copy calibration: 3 copies of", n_bytes, "bytes")
-    del a, b
     dtype = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
     case = I.point_case(n=8192, nsteps=5000)
     s = fdw.solver_for_case(case, dtype=dtype)
+    del case
     s.step(400, energy=True)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        s.get_state()
     torch.cuda.synchronize()
     log("profile run done:", dtype_name, "K", s.config(fdw.FDW_CFG_TIME_BLOCK), "C",
         s.config(fdw.FDW_CFG_LANE_COLUMNS), "S", s.config(fdw.FDW_CFG_SEGMENT_ROWS))
     s.close()
 
 
-def summarize_profile(d: str, name: str, command: str):
-    """Collects kernel statistics and (if present) FETCH_SIZE / WRITE_SIZE counter rows from
-    rocprofv3 CSV output under d into profiles/<name>.txt."""
+def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32"):
+    """Collects kernel statistics and FETCH_SIZE / WRITE_SIZE counter rows from rocprofv3 CSV
+    output under `dirs` into profiles/<name>.txt.  When both counters were taken for the
+    streaming kernel and for the calibration copy (k_copy_out: n*n words read and written per
+    dispatch), the calibrated HBM bytes per streaming launch go to profiles/<name>.json."""
     import csv
     import glob
 
     lines = [f"# {name}", f"command: {command}", ""]
-    stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
-    for f in stats:
-        rows = list(csv.DictReader(open(f)))
-        lines.append(f"kernel stats ({os.path.relpath(f, d)}):")
-        lines.append("name | calls | total_ns | avg_ns | pct")
-        for r in rows[:12]:
-            lines.append(f"{r.get('Name','')[:90]} | {r.get('Calls','')} | {r.get('TotalDurationNs','')} | "
-                         f"{r.get('AverageNs','')} | {r.get('Percentage','')}")
-        lines.append("")
-    counters = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
     summary = {}
-    for f in counters:
-        for r in csv.DictReader(open(f)):
-            kname = r.get("Kernel_Name", "")
-            cname = r.get("Counter_Name", "")
-            try:
-                val = float(r.get("Counter_Value", "nan"))
-            except ValueError:
-                continue
-            key = ("copy" if ("copy" in kname.lower() or "elementwise" in kname.lower()) else
-                   ("k_step" if "k_step" in kname else None))
-            if key is None:
-                continue
-            summary.setdefault((key, cname), []).append(val)
+    for d in dirs:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+            rows = list(csv.DictReader(open(f)))
+            lines.append(f"kernel stats ({os.path.basename(d)}):")
+            lines.append("name | calls | total_ns | avg_ns | pct")
+            for r in rows[:12]:
+                lines.append(f"{r.get('Name', '')[:110]} | {r.get('Calls', '')} | {r.get('TotalDurationNs', '')} | "
+                             f"{r.get('AverageNs', '')} | {r.get('Percentage', '')}")
+            lines.append("")
+        for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            for r in csv.DictReader(open(f)):
+                kname = r.get("Kernel_Name", "")
+                cname = r.get("Counter_Name", "")
+                try:
+                    val = float(r.get("Counter_Value", "nan"))
+                except ValueError:
+                    continue
+                key = "copy" if "k_copy_out" in kname else ("k_step" if "k_step" in kname else None)
+                if key is None:
+                    continue
+                summary.setdefault((key, cname), []).append(val)
     if summary:
-        lines.append("counters (per dispatch, mean over dispatches):")
+        lines.append("counters (KiB per dispatch, mean over dispatches):")
         for (k, c), v in sorted(summary.items()):
-            lines.append(f"{k} {c} mean {sum(v) / len(v):.1f} KiB over {len(v)} dispatches")
+            lines.append(f"{k} {c} mean {sum(v) / len(v):.1f} over {len(v)} dispatches")
+    need = [("copy", "FETCH_SIZE"), ("copy", "WRITE_SIZE"), ("k_step", "FETCH_SIZE"), ("k_step", "WRITE_SIZE")]
+    if all(k in summary for k in need):
+        mean = {k: sum(summary[k]) / len(summary[k]) for k in need}
+        n = 8192
+        es = 4 if dtype_name == "f32" else 8
+        copy_kib = n * n * es / 1024.0
+        f_fetch = copy_kib / mean[("copy", "FETCH_SIZE")]
+        f_write = copy_kib / mean[("copy", "WRITE_SIZE")]
+        read_b = mean[("k_step", "FETCH_SIZE")] * f_fetch * 1024.0
+        write_b = mean[("k_step", "WRITE_SIZE")] * f_write * 1024.0
+        alg = 5 * es * n * n
+        lines += ["", f"calibration: copy of {n}x{n} words reads and writes {copy_kib:.0f} KiB; "
+                      f"factors fetch {f_fetch:.4f}, write {f_write:.4f}",
+                  f"streaming kernel: {read_b / 1e6:.1f} MB read + {write_b / 1e6:.1f} MB written per launch "
+                  f"(algorithmic {alg / 1e6:.1f} MB: 3 words read, 2 written per node)"]
+        js = {"kernel_source_hash": kernel_source_hash(), "bytes_per_launch": round(read_b + write_b),
+              "read_bytes": round(read_b), "write_bytes": round(write_b), "algorithmic_bytes": alg,
+              "fetch_factor": f_fetch, "write_factor": f_write, "command": command}
+        with open(os.path.join(ROOT, "profiles", name + ".json"), "w") as fh:
+            json.dump(js, fh, indent=1)
     out = os.path.join(ROOT, "profiles", name + ".txt")
     open(out, "w").write("\n".join(lines) + "\n")
     print(out)
@@ -284,11 +305,12 @@ def summarize_profile(d: str, name: str, command: str):
 def main():
     if "--summarize-profile" in sys.argv:
         ap = argparse.ArgumentParser()
-        ap.add_argument("--summarize-profile", required=True)
+        ap.add_argument("--summarize-profile", required=True, nargs="+")
         ap.add_argument("--out", required=True)
         ap.add_argument("--command", default="")
+        ap.add_argument("--dtype", default="f32")
         a = ap.parse_args()
-        summarize_profile(a.summarize_profile, a.out, a.command)
+        summarize_profile(a.summarize_profile, a.out, a.command, a.dtype)
         return
     if "--profile-run" in sys.argv:
         ap = argparse.ArgumentParser()
@@ -324,7 +346,7 @@ def main():
     per_launch_bytes = 5 * 4 * nodes  # read u, du, h; write u, du (FP32 words) per streaming launch
     avg_launch_s = f32["kernel_ms"] / 1e3 / max(f32["launches"], 1)
     achieved = per_launch_bytes / avg_launch_s / 1e9
-    traffic = load_traffic("k_step_f32_point8192_traffic.json", nodes)
+    traffic = load_traffic("k_step_f32_point8192.json", nodes)
     roof = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -374,11 +396,16 @@ def main():
         log("batched family")
         fam = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
         log(json.dumps(fam))
+        famp = family_bench(fdw, torch, I, 1, 1, persistent=True)
+        log(json.dumps(famp))
         out["batched"] = {"value": round(fam["ups"], 1), "unit": "grid-point updates/s", "members": 32,
                           "ms_per_step": round(fam["sec"] * 1e3, 2), "time_block": fam["K"],
                           "alg_GBs": round(fam["alg_GBs"], 1), "frac": round(fam["alg_GBs"] / HBM_PEAK_GBS, 4),
+                          "persistent_value": round(famp["ups"], 1),
                           "workload": "32 regularisations, eps log-spaced 0.1 .. 2dx, delta line / Heaviside jump, "
-                                      "512^2-4096^2, 2000 steps, FP32, one persistent launch"}
+                                      "512^2-4096^2, 2000 steps, FP32; value: one launch per time block covering "
+                                      "all members, replayed from a hipGraph; persistent_value: one cooperative "
+                                      "launch per call with a grid barrier between time blocks"}
         torch.cuda.empty_cache()
         log("adjoint 2048^2 fp64 x 4000")
         adj = adjoint_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)

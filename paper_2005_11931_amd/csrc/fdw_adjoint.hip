@@ -42,6 +42,8 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     constexpr int Hx = ((K + C - 1) / C) * C;
     constexpr int Wv = kWaveSize * C - 2 * Hx;
     constexpr int U = RowUnroll<K>::U;
+    constexpr int NB = RowUnroll<K>::NB;
+    static_assert(U % NB == 0 && U % K == 0 && U % 2 == 0, "row unroll");
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
     if (wave >= a.waves) return;
@@ -102,10 +104,10 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     T Gl[K][C];         // y flux of lam^{m-s+1} below row r
     double Py[K][C];    // y face products below row r
     double GX[K][C], GY[K][C];  // gradient of rows j-1 .. j-K (by row modulo K); GY only if SPLIT
-    double gbuf[2][C], g2buf[2][C];  // accumulator rows loaded one iteration ahead
+    double gbuf[NB][C], g2buf[NB][C];  // accumulator rows, loaded NB - 1 iterations ahead
     T FXr[K][C], FYr[K][C];
     T hprev[C], hyprev[C];
-    T bu[2][C], bd[2][C], bl[2][C], bm[2][C], bh[2][C], bhy[2][C];
+    T bu[NB][C], bd[NB][C], bl[NB][C], bm[NB][C], bh[NB][C], bhy[NB][C];  // rows by row modulo NB
     // receiver range [RPb, RPe) of the rows j-1 .. j-K (by row modulo K), looked up once per
     // row when it enters level 1
     int RPb[K], RPe[K];
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
         }
         hprev[c] = hyprev[c] = T(0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NB; ++q) {
             bu[q][c] = bd[q][c] = bl[q][c] = bm[q][c] = bh[q][c] = bhy[q][c] = T(0);
             gbuf[q][c] = g2buf[q][c] = 0.0;
         }
@@ -144,17 +146,23 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
         buffer_row<double, C>(rg1, goff, g1);
         if (split) buffer_row<double, C>(rg2, goff, g2);
     };
-    load_row(jb, bu[0], bd[0], bl[0], bm[0], bh[0], bhy[0]);
-    load_g(jb - K, gbuf[0], g2buf[0]);
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) {
+        load_row(jb + q, bu[q], bd[q], bl[q], bm[q], bh[q], bhy[q]);
+        load_g(jb + q - K, gbuf[q], g2buf[q]);
+    }
     const int nblk = (r1 + K - jb + U - 1) / U;
 
     for (int blk = 0; blk < nblk; ++blk) {
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const int j = jb + blk * U + s;
-            const int pb = s & 1;
-            load_row(j + 1, bu[pb ^ 1], bd[pb ^ 1], bl[pb ^ 1], bm[pb ^ 1], bh[pb ^ 1], bhy[pb ^ 1]);
-            load_g(j + 1 - K, gbuf[pb ^ 1], g2buf[pb ^ 1]);
+            const int pb = s % NB;
+            {
+                const int pn = (s + NB - 1) % NB;
+                load_row(j + NB - 1, bu[pn], bd[pn], bl[pn], bm[pn], bh[pn], bhy[pn]);
+                load_g(j + NB - 1 - K, gbuf[pn], g2buf[pn]);
+            }
             // coefficient faces of row j-1
             {
                 const int q = pmod(s - 1, K);

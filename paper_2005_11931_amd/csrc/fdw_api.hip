@@ -186,14 +186,14 @@ int choose_K(const fdw_ctx* c)
 int choose_S(const fdw_ctx* c)
 {
     if (c->S_cfg > 0) return c->S_cfg;
-    // Many short work items: aim at about 8192 streaming waves (several rounds of the 3072
-    // wave slots) for the largest member, with segments of 16 to 64 rows; a longer segment
-    // saves little of the 2K-row pipeline fill and leaves the chip with too few waves.
+    // About 4600 streaming waves (one and a half rounds of the 3072 wave slots of the 8-step
+    // kernel) for the largest member, with segments of 16 to 128 rows: longer segments spend
+    // less on the 2K halo rows every segment recomputes, but fewer waves leave latency exposed.
     int best = kMinSegRows;
     for (const HostMember& hm : c->m) {
         const int64_t strips = max_strips(hm.nx);
-        int64_t S = (hm.ny * strips + 8191) / 8192;
-        S = std::min<int64_t>(64, std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8));
+        int64_t S = (hm.ny * strips + 4607) / 4608;
+        S = std::min<int64_t>(128, std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8));
         best = std::max(best, (int)S);
     }
     return best;
@@ -464,7 +464,7 @@ template <typename T>
 int run_persistent(fdw_ctx* c, int64_t steps)
 {
     const int Kc = choose_K(c);
-    const int K = Kc >= 4 ? 4 : (Kc >= 2 ? 2 : 1);
+    const int K = Kc >= 8 ? 8 : (Kc >= 4 ? 4 : (Kc >= 2 ? 2 : 1));  // time blocks of the persistent kernel
     int face_mode = c->m[0].face;
     for (const HostMember& hm : c->m)
         if (hm.face != face_mode) return fail(c, FDW_ENOTSUP, "persistent batch needs one coefficient layout");

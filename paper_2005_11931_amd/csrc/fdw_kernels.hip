@@ -94,8 +94,16 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table,
     const int m = first + blockIdx.y;
     const MemberDev& M = table[m];
     const double* p = M.epart + (size_t)t * M.epart_stride;
-    double s = 0.0;
-    for (int w = threadIdx.x; w < M.waves; w += 256) s += p[w];
+    // four independent chains so that the loads of a thread are in flight together
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nw = M.waves;
+    int w = threadIdx.x;
+    for (; w + 3 * 256 < nw; w += 4 * 256) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] += p[w + q * 256];
+    }
+    for (; w < nw; w += 256) s4[0] += p[w];
+    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();

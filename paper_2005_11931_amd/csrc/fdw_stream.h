@@ -147,13 +147,16 @@ __device__ __forceinline__ double wave_sum(double v)
 // F_c = fx_{c+1/2} (u_{c+1} - u_c), and the y part with the flux G_r = fy_{r+1/2}
 // (u_{r+1} - u_r) carried over from the previous row: sx = F_c - F_{c-1}, sy = G_r - G_{r-1}.
 // Since fx_{c-1/2}(u_{c-1} - u_c) = -F_{c-1} exactly, this is bit-identical to summing the
-// two opposite-face terms of every node.  Rings are indexed by the row modulo 2 and K; the
-// row loop is unrolled by lcm(2, K) so that every ring index is a compile-time constant.
-// The input row j+1 is loaded while row j is being processed.
+// two opposite-face terms of every node.  Rings are indexed by the row modulo 2 and K, and the
+// loaded input rows by the row modulo NB; the row loop is unrolled by lcm(2, K, NB) so that
+// every ring index is a compile-time constant.  Input rows are loaded NB - 1 rows ahead of
+// their use: one row of loads per wave in flight is far too little to cover the HBM latency
+// at the occupancy these register footprints allow.
 // ------------------------------------------------------------------------------------------
 template <int K>
 struct RowUnroll {
-    static constexpr int U = (K % 2 == 0) ? K : 2 * K;
+    static constexpr int NB = (K % 2 == 0) ? 4 : 2;  // row buffers (odd K: keep the unroll at 2K)
+    static constexpr int U = (K % 2 == 0) ? ((K % 4 == 0) ? K : 2 * K) : 2 * K;
 };
 __host__ __device__ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
@@ -202,6 +205,8 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     constexpr int Hx = ((K + C - 1) / C) * C;   // halo columns on each side (multiple of C)
     constexpr int Wv = kWaveSize * C - 2 * Hx;  // owned columns per strip
     constexpr int U = RowUnroll<K>::U;
+    constexpr int NB = RowUnroll<K>::NB;
+    static_assert(U % NB == 0 && U % K == 0 && U % 2 == 0, "row unroll");
     const int lane = threadIdx.x & 63;
 
     const int nx = M.nx, ny = M.ny, ld = M.ld;
@@ -246,7 +251,7 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     T FYr[K][C];    // y-face sums between those rows and the next
     T hprev[C];     // coefficient row j-1 (nodal h, or the x-face row in the face layout)
     T hyprev[C];    // face layout: y-face row j-1
-    T bu[2][C], bd[2][C], bh[2][C], bhy[2][C];  // loaded rows (double-buffered)
+    T bu[NB][C], bd[NB][C], bh[NB][C], bhy[NB][C];  // loaded rows j .. j+NB-1 (by row modulo NB)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
 #pragma unroll
@@ -258,7 +263,7 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
         }
         hprev[c] = hyprev[c] = T(0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) bu[q][c] = bd[q][c] = bh[q][c] = bhy[q][c] = T(0);
+        for (int q = 0; q < NB; ++q) bu[q][c] = bd[q][c] = bh[q][c] = bhy[q][c] = T(0);
     }
     double acc[K];
 #pragma unroll
@@ -275,7 +280,8 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
         buffer_row<T, C>(rh, off, h);
         if (FACE) buffer_row<T, C>(rhy, off, hy);
     };
-    load_row(jb, bu[0], bd[0], bh[0], bhy[0]);
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q) load_row(jb + q, bu[q], bd[q], bh[q], bhy[q]);
 
     for (int blk = 0; blk < nblk; ++blk) {
         T eb[K];
@@ -284,9 +290,12 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const int j = jb + blk * U + s;
-            const int pb = s & 1;  // buffer holding row j
-            // prefetch row j+1
-            load_row(j + 1, bu[pb ^ 1], bd[pb ^ 1], bh[pb ^ 1], bhy[pb ^ 1]);
+            const int pb = s % NB;  // buffer holding row j
+            // prefetch row j+NB-1 into the buffer row j-1 used
+            {
+                const int pn = (s + NB - 1) % NB;
+                load_row(j + NB - 1, bu[pn], bd[pn], bh[pn], bhy[pn]);
+            }
 
             // ---- coefficient faces of row j-1 into the ring (index (j-1-jb) mod K)
             {
@@ -557,7 +566,8 @@ static int persistent_blocks_kc(int face_mode)
     return per_cu * cus;
 }
 
-template <typename T, int C>
+// time blocks 1, 2, 4 and (when the configuration allows it) 8
+template <typename T, int C, int KMAX>
 static hipError_t launch_persistent_c(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
                                       hipStream_t s)
 {
@@ -565,16 +575,20 @@ static hipError_t launch_persistent_c(const StepArgs& a, int K, int face_mode, i
     case 1: return launch_persistent_kc<T, 1, C>(a, face_mode, phases, grid, bar, s);
     case 2: return launch_persistent_kc<T, 2, C>(a, face_mode, phases, grid, bar, s);
     case 4: return launch_persistent_kc<T, 4, C>(a, face_mode, phases, grid, bar, s);
+    case 8:
+        return KMAX >= 8 ? launch_persistent_kc<T, (KMAX >= 8 ? 8 : 1), C>(a, face_mode, phases, grid, bar, s)
+                         : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
-template <typename T, int C>
+template <typename T, int C, int KMAX>
 static int persistent_max_c(int K, int face_mode)
 {
     switch (K) {
     case 1: return persistent_blocks_kc<T, 1, C>(face_mode);
     case 2: return persistent_blocks_kc<T, 2, C>(face_mode);
     case 4: return persistent_blocks_kc<T, 4, C>(face_mode);
+    case 8: return KMAX >= 8 ? persistent_blocks_kc<T, (KMAX >= 8 ? 8 : 1), C>(face_mode) : 0;
     default: return 0;
     }
 }
