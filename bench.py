@@ -195,20 +195,22 @@ def adjoint_bench(fdw, torch, I, steps, warmup):
 
 def cpu_baseline(I, budget_s=15.0):
     """The FP64 oracle on the host cores: first k steps of the same 8192^2 workload, k chosen
-    from a 2-step calibration run so that the timed run takes about budget_s seconds."""
+    from two calibration runs (3 and 13 steps; their difference removes the per-call set-up)
+    so that the timed run takes about budget_s seconds."""
     import oracle
 
     n = 8192
     case = I.point_case(n=n, nsteps=5000)
     oracle.forward_case(case, nsteps=2)  # warm-up (page faults, thread start)
     t0 = time.perf_counter()
-    oracle.forward_case(case, nsteps=4)
-    t4 = time.perf_counter() - t0
+    oracle.forward_case(case, nsteps=3)
+    t3 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.forward_case(case, nsteps=2)
-    t2 = time.perf_counter() - t0
-    per_step = max((t4 - t2) / 2.0, 1e-3)
-    k = max(4, int(budget_s / per_step))
+    oracle.forward_case(case, nsteps=13)
+    t13 = time.perf_counter() - t0
+    per_step = max((t13 - t3) / 10.0, 1e-3)
+    setup = max(t3 - 3 * per_step, 0.0)
+    k = max(4, int((budget_s - setup) / per_step))
     t0 = time.perf_counter()
     oracle.forward_case(case, nsteps=k)
     dt = time.perf_counter() - t0

@@ -63,8 +63,12 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     const double axd = a.ax, ayd = a.ay;
     constexpr bool split = SPLIT != 0;
 
-    const int jb = r0 - K;
-    const int jbase = max(jb, 0);
+    // even segments stream downwards, odd ones upwards, as in the forward kernel (the shared
+    // halo rows of two neighbouring segments are then read at about the same time); position p
+    // of the stream is row rfirst + dir * p, and the result is the same bit for bit
+    const int dir = (seg & 1) ? -1 : 1;
+    const int rfirst = (dir > 0) ? r0 - K : r1 + K - 1;
+    const int jbase = max(r0 - K, 0);
     const size_t base_el = (size_t)jbase * ld;
     const size_t span = (size_t)(ny - jbase) * ld * sizeof(T);
     const unsigned int nbytes = (unsigned int)min(span, (size_t)kBufferOutOfRange - 16);
@@ -103,12 +107,12 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     T Gu[K][C];         // y flux of u^{m-s} below row r (level s stores at s-1)
     T Gl[K][C];         // y flux of lam^{m-s+1} below row r
     double Py[K][C];    // y face products below row r
-    double GX[K][C], GY[K][C];  // gradient of rows j-1 .. j-K (by row modulo K); GY only if SPLIT
+    double GX[K][C], GY[K][C];  // gradient of rows p-1 .. p-K (by position modulo K); GY only if SPLIT
     double gbuf[NB][C], g2buf[NB][C];  // accumulator rows, loaded NB - 1 iterations ahead
     T FXr[K][C], FYr[K][C];
     T hprev[C], hyprev[C];
     T bu[NB][C], bd[NB][C], bl[NB][C], bm[NB][C], bh[NB][C], bhy[NB][C];  // rows by row modulo NB
-    // receiver range [RPb, RPe) of the rows j-1 .. j-K (by row modulo K), looked up once per
+    // receiver range [RPb, RPe) of the rows p-1 .. p-K (by position modulo K), looked up once per
     // row when it enters level 1
     int RPb[K], RPe[K];
 #pragma unroll
@@ -131,8 +135,9 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
             gbuf[q][c] = g2buf[q][c] = 0.0;
         }
     }
-    auto load_row = [&](int j, T (&u)[C], T (&d)[C], T (&l)[C], T (&m)[C], T (&h)[C], T (&hy)[C]) {
-        const unsigned int off = (unsigned int)(j - jbase) * row_bytes + lane_col;
+    auto load_row = [&](int p, T (&u)[C], T (&d)[C], T (&l)[C], T (&m)[C], T (&h)[C], T (&hy)[C]) {
+        const int j = rfirst + dir * p;
+        const unsigned int off = (j < jbase) ? kBufferOutOfRange : (unsigned int)(j - jbase) * row_bytes + lane_col;
         buffer_row<T, C>(ru, off, u);
         buffer_row<T, C>(rd, off, d);
         buffer_row<T, C>(rl, off, l);
@@ -140,37 +145,39 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
         buffer_row<T, C>(rh, off, h);
         if (FACE) buffer_row<T, C>(rhy, off, hy);
     };
-    // accumulator row j-K+1 ... of the row completed one iteration later
-    auto load_g = [&](int j, double (&g1)[C], double (&g2)[C]) {
-        const unsigned int goff = (unsigned int)(j - jbase) * grow_bytes + glane_col;
+    // accumulator row of stream position p (the row completed NB - 1 iterations later)
+    auto load_g = [&](int p, double (&g1)[C], double (&g2)[C]) {
+        const int j = rfirst + dir * p;
+        const unsigned int goff = (j < jbase) ? kBufferOutOfRange : (unsigned int)(j - jbase) * grow_bytes + glane_col;
         buffer_row<double, C>(rg1, goff, g1);
         if (split) buffer_row<double, C>(rg2, goff, g2);
     };
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q) {
-        load_row(jb + q, bu[q], bd[q], bl[q], bm[q], bh[q], bhy[q]);
-        load_g(jb + q - K, gbuf[q], g2buf[q]);
+        load_row(q, bu[q], bd[q], bl[q], bm[q], bh[q], bhy[q]);
+        load_g(q - K, gbuf[q], g2buf[q]);
     }
-    const int nblk = (r1 + K - jb + U - 1) / U;
+    const int nblk = (r1 - r0 + 2 * K + U - 1) / U;
 
     for (int blk = 0; blk < nblk; ++blk) {
 #pragma unroll
         for (int s = 0; s < U; ++s) {
-            const int j = jb + blk * U + s;
+            const int p = blk * U + s;  // stream position of the row loaded last
             const int pb = s % NB;
             {
                 const int pn = (s + NB - 1) % NB;
-                load_row(j + NB - 1, bu[pn], bd[pn], bl[pn], bm[pn], bh[pn], bhy[pn]);
-                load_g(j + NB - 1 - K, gbuf[pn], g2buf[pn]);
+                load_row(p + NB - 1, bu[pn], bd[pn], bl[pn], bm[pn], bh[pn], bhy[pn]);
+                load_g(p + NB - 1 - K, gbuf[pn], g2buf[pn]);
             }
-            // coefficient faces of row j-1
+            // coefficient faces of row p-1 (the y face between rows p-1 and p is stored with
+            // the upper of the two grid rows)
             {
                 const int q = pmod(s - 1, K);
                 if (FACE) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         FXr[q][c] = hprev[c];
-                        FYr[q][c] = hyprev[c];
+                        FYr[q][c] = (dir > 0) ? hyprev[c] : bhy[pb][c];
                         hprev[c] = bh[pb][c];
                         hyprev[c] = bhy[pb][c];
                     }
@@ -185,7 +192,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
                 }
             }
-            // level 0 (time m): row j
+            // level 0 (time m): row p
             {
                 const int p0 = pmod(s, 2);
 #pragma unroll
@@ -198,12 +205,12 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
             }
 #pragma unroll
             for (int t = 1; t <= K; ++t) {
-                const int r = j - t;
+                const int r = rfirst + dir * (p - t);  // grid row of stream position p - t
                 const int pr = pmod(s - t, 2);
                 const int pr1 = pmod(s - t + 1, 2);
                 const int q = pmod(s - t, K);
                 const bool rin = (r >= 1) && (r <= ny - 2);
-                const bool r1in = (r + 1 >= 1) && (r + 1 <= ny - 2);
+                const bool r1in = (r + dir >= 1) && (r + dir <= ny - 2);  // the next row in the stream
                 const bool rown = (r >= r0) && (r < r1);
                 const int64_t n = a.n_top - t;  // time of this level's forward state
                 const double w = (n == 0) ? 0.5 : 1.0;
@@ -290,10 +297,10 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     store_pack<T, C>(mout + off, nm);
                 }
             }
-            // row j-K has all K contributions (ring index (j-K-jb) mod K = s mod K)
+            // the row at position p-K has all K contributions (ring index (p-K) mod K = s mod K)
             {
                 const int qd = pmod(s, K);
-                const int r = j - K;
+                const int r = rfirst + dir * (p - K);
                 if (r >= r0 && r < r1 && lane_owned) {
                     const size_t off = (size_t)(ptrdiff_t)r * ld + (size_t)(ptrdiff_t)cb;
                     double o1[C], o2[C];

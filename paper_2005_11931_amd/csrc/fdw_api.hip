@@ -186,14 +186,16 @@ int choose_K(const fdw_ctx* c)
 int choose_S(const fdw_ctx* c)
 {
     if (c->S_cfg > 0) return c->S_cfg;
-    // About 4600 streaming waves (one and a half rounds of the 3072 wave slots of the 8-step
-    // kernel) for the largest member, with segments of 16 to 128 rows: longer segments spend
-    // less on the 2K halo rows every segment recomputes, but fewer waves leave latency exposed.
+    // Segments of 16 K rows (the 2K halo rows of a segment are then 1/8 of it, and half of
+    // them are usually shared with the neighbouring segment through L2), but short enough to
+    // give about 4600 streaming waves (one and a half rounds of the wave slots) for the
+    // largest member; at least 16 rows.
+    const int K = choose_K(c);
     int best = kMinSegRows;
     for (const HostMember& hm : c->m) {
         const int64_t strips = max_strips(hm.nx);
         int64_t S = (hm.ny * strips + 4607) / 4608;
-        S = std::min<int64_t>(128, std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8));
+        S = std::min<int64_t>(16 * K, std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8));
         best = std::max(best, (int)S);
     }
     return best;
@@ -1009,6 +1011,7 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
     invalidate_graphs(c);
+    c->S_eff = choose_S(c);  // the automatic segment length depends on the time block
     for (int i = 0; i < c->count; ++i) sync_member_dev(c, i);
     return layout_for_K(c, choose_K(c), c->S_eff);
 }

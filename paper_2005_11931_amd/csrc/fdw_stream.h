@@ -142,13 +142,15 @@ __device__ __forceinline__ double wave_sum(double v)
 // ------------------------------------------------------------------------------------------
 // One streaming work item: member M, strip, segment; K time levels; C columns per lane.
 //
-// Level t (t = 1..K) computes row r = j - t at iteration j from level t-1's rows r and r+1
-// (u) and row r (du).  The x part of the operator is written with one flux per face,
+// The work item streams its rows in one direction (down for even segments, up for odd ones);
+// at stream position p, level t (t = 1..K) computes the row at position p - t from level
+// t-1's rows at positions p - t and p - t + 1 (u) and p - t (du).  Below, the rows are
+// written as for the downward direction.  The x part of the operator is written with one flux per face,
 // F_c = fx_{c+1/2} (u_{c+1} - u_c), and the y part with the flux G_r = fy_{r+1/2}
 // (u_{r+1} - u_r) carried over from the previous row: sx = F_c - F_{c-1}, sy = G_r - G_{r-1}.
 // Since fx_{c-1/2}(u_{c-1} - u_c) = -F_{c-1} exactly, this is bit-identical to summing the
-// two opposite-face terms of every node.  Rings are indexed by the row modulo 2 and K, and the
-// loaded input rows by the row modulo NB; the row loop is unrolled by lcm(2, K, NB) so that
+// two opposite-face terms of every node.  Rings are indexed by the position modulo 2 and K, and the
+// loaded input rows by the position modulo NB; the row loop is unrolled by lcm(2, K, NB) so that
 // every ring index is a compile-time constant.  Input rows are loaded NB - 1 rows ahead of
 // their use: one row of loads per wave in flight is far too little to cover the HBM latency
 // at the occupancy these register footprints allow.
@@ -231,9 +233,15 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     const T ax = (T)M.ax, ay = (T)M.ay;
     const int64_t n0 = ctx_step + M.n_offset;
 
-    // buffer resources starting at the first streamed row inside the grid
-    const int jb = r0 - K;
-    const int jbase = max(jb, 0);
+    // Even segments stream downwards (rows r0-K .. r1+K-1), odd ones upwards (r1+K-1 ..
+    // r0-K): two neighbouring segments then pass over the 2K rows both of them read at about
+    // the same time - both at their start or both at their end - so that the second read of
+    // those rows usually hits L2.  Position p of the stream is row rfirst + dir * p.  The
+    // result does not depend on the direction, bit for bit (see the y-flux below).
+    const int dir = (seg & 1) ? -1 : 1;
+    const int rfirst = (dir > 0) ? r0 - K : r1 + K - 1;
+    // buffer resources starting at the lowest streamed row inside the grid
+    const int jbase = max(r0 - K, 0);
     const size_t base_el = (size_t)jbase * ld;
     const size_t span = (size_t)(ny - jbase) * ld * sizeof(T);
     const unsigned int nbytes = (unsigned int)min(span, (size_t)kBufferOutOfRange - 16);
@@ -244,14 +252,15 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     const unsigned int row_bytes = (unsigned int)(ld * (int)sizeof(T));
     const unsigned int lane_col = lane_live ? (unsigned int)(cb * (int)sizeof(T)) : kBufferOutOfRange;
 
-    T Ur[K][2][C];  // level t at rows of parity 0/1 (relative to the first row jb)
+    // (rings are indexed by stream position p, "row p" meaning the row at position p)
+    T Ur[K][2][C];  // level t at rows of stream parity 0/1
     T Dr[K][2][C];
-    T Gy[K][C];     // Gy[t-1]: y-flux of level t-1 below the row level t computes next
-    T FXr[K][C];    // x-face sums of the rows j-K .. j-1 (by row modulo K)
-    T FYr[K][C];    // y-face sums between those rows and the next
-    T hprev[C];     // coefficient row j-1 (nodal h, or the x-face row in the face layout)
-    T hyprev[C];    // face layout: y-face row j-1
-    T bu[NB][C], bd[NB][C], bh[NB][C], bhy[NB][C];  // loaded rows j .. j+NB-1 (by row modulo NB)
+    T Gy[K][C];     // Gy[t-1]: y-flux of level t-1 across the face before the row level t computes next
+    T FXr[K][C];    // x-face sums of the rows p-K .. p-1 (by position modulo K)
+    T FYr[K][C];    // y-face sums between those rows and the next one in the stream
+    T hprev[C];     // coefficient row p-1 (nodal h, or the x-face row in the face layout)
+    T hyprev[C];    // face layout: y-face row p-1
+    T bu[NB][C], bd[NB][C], bh[NB][C], bhy[NB][C];  // loaded rows p .. p+NB-1 (by position modulo NB)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
 #pragma unroll
@@ -269,19 +278,20 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
 #pragma unroll
     for (int t = 0; t < K; ++t) acc[t] = 0.0;
 
-    // Rows jb .. r1+K-1 are streamed (rounded up to whole unrolled blocks; rows outside the
+    // r1 - r0 + 2K rows are streamed (rounded up to whole unrolled blocks; rows outside the
     // grid load as zeros and are never stored).
-    const int nblk = (r1 + K - jb + U - 1) / U;
+    const int nblk = (r1 - r0 + 2 * K + U - 1) / U;
     const size_t lane_off = (size_t)(ptrdiff_t)cb;
-    auto load_row = [&](int j, T (&u)[C], T (&d)[C], T (&h)[C], T (&hy)[C]) {
-        const unsigned int off = (unsigned int)(j - jbase) * row_bytes + lane_col;
+    auto load_row = [&](int p, T (&u)[C], T (&d)[C], T (&h)[C], T (&hy)[C]) {
+        const int j = rfirst + dir * p;
+        const unsigned int off = (j < jbase) ? kBufferOutOfRange : (unsigned int)(j - jbase) * row_bytes + lane_col;
         buffer_row<T, C>(ru, off, u);
         buffer_row<T, C>(rd, off, d);
         buffer_row<T, C>(rh, off, h);
         if (FACE) buffer_row<T, C>(rhy, off, hy);
     };
 #pragma unroll
-    for (int q = 0; q < NB - 1; ++q) load_row(jb + q, bu[q], bd[q], bh[q], bhy[q]);
+    for (int q = 0; q < NB - 1; ++q) load_row(q, bu[q], bd[q], bh[q], bhy[q]);
 
     for (int blk = 0; blk < nblk; ++blk) {
         T eb[K];
@@ -289,22 +299,23 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
         for (int t = 0; t < K; ++t) eb[t] = T(0);
 #pragma unroll
         for (int s = 0; s < U; ++s) {
-            const int j = jb + blk * U + s;
-            const int pb = s % NB;  // buffer holding row j
-            // prefetch row j+NB-1 into the buffer row j-1 used
+            const int p = blk * U + s;  // stream position of the row loaded last
+            const int pb = s % NB;      // buffer holding row p
+            // prefetch row p+NB-1 into the buffer row p-1 used
             {
                 const int pn = (s + NB - 1) % NB;
-                load_row(j + NB - 1, bu[pn], bd[pn], bh[pn], bhy[pn]);
+                load_row(p + NB - 1, bu[pn], bd[pn], bh[pn], bhy[pn]);
             }
 
-            // ---- coefficient faces of row j-1 into the ring (index (j-1-jb) mod K)
+            // ---- coefficient faces of row p-1 into the ring (index (p-1) mod K); the y face
+            // between rows p-1 and p is stored with the upper of the two grid rows
             {
                 const int q = pmod(s - 1, K);
                 if (FACE) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         FXr[q][c] = hprev[c];
-                        FYr[q][c] = hyprev[c];
+                        FYr[q][c] = (dir > 0) ? hyprev[c] : bhy[pb][c];
                         hprev[c] = bh[pb][c];
                         hyprev[c] = bhy[pb][c];
                     }
@@ -319,7 +330,7 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
                     for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
                 }
             }
-            // ---- level 0: row j of the input state
+            // ---- level 0: row p of the input state
             {
                 const int p0 = pmod(s, 2);
 #pragma unroll
@@ -331,9 +342,9 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
             // ---- levels 1..K
 #pragma unroll
             for (int t = 1; t <= K; ++t) {
-                const int r = j - t;
+                const int r = rfirst + dir * (p - t);  // grid row of stream position p - t
                 const int pr = pmod(s - t, 2);      // parity index of row r
-                const int pr1 = pmod(s - t + 1, 2); // ... of row r+1
+                const int pr1 = pmod(s - t + 1, 2); // ... of the next row in the stream, r + dir
                 const int q = pmod(s - t, K);       // coefficient ring index of row r
                 const bool rin = (r >= 1) && (r <= ny - 2);
                 const bool rown = (r >= r0) && (r < r1);
@@ -348,6 +359,9 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
                 T nu[C], nd[C], L[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
+                    // Gn = fy (u_{r+dir} - u_r): downwards this is F_{r+1/2}, upwards it is
+                    // -F_{r-1/2} exactly (negation is exact), and Gy holds the previous row's
+                    // Gn; so Gn - Gy is F_{r+1/2} - F_{r-1/2} bit for bit in both directions
                     const T Gn = FYr[q][c] * (Ur[t - 1][pr1][c] - Ur[t - 1][pr][c]);
                     const T sx = F[c] - ((c > 0) ? F[c - 1] : Fl);
                     const T sy = Gn - Gy[t - 1][c];
