@@ -102,6 +102,75 @@ def forward_bench(fdw, torch, I, dtype, steps, warmup, n=8192, nsteps=5000):
                 n=n, nsteps=nsteps)
 
 
+def copy_bench(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of torch's copy of a
+    1 GiB buffer: the practical ceiling a streaming kernel is compared with."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2.0 * nbytes / dt / 1e9
+
+
+def small_bench(fdw, torch, I, steps):
+    """The 256^2 FP64 line workload (1000 steps + energy): cache-resident and launch-bound,
+    reported as microseconds per step with the launch sequence replayed from a graph."""
+    case = I.line_case(n=256, nsteps=1000)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
+    h = torch.as_tensor(case.h1, device="cuda")
+    e = torch.empty((1, case.nsteps), dtype=torch.float64, device="cuda")
+
+    def one():
+        s.reset()
+        s.step_into(case.nsteps, e)
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(steps, 5)):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 5)
+    K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    s.close()
+    del h
+    return dict(us_per_step=dt / case.nsteps * 1e6, K=K)
+
+
+def largest_bench(fdw, torch, I, steps):
+    """The largest single-GPU workload: 16384^2 FP32 bathymetry + delta ridge, 10^4 steps."""
+    n, nsteps = 16384, 10000
+    case = I.bathymetry_case(n=n, nsteps=nsteps)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+    h = torch.as_tensor(case.h1, dtype=torch.float32, device="cuda")
+    del case
+    updates = (n - 2) * (n - 2) * nsteps
+
+    def one():
+        s.set_coeff(h)
+        s.step(nsteps)
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, steps)):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(1, steps)
+    K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    s.close()
+    return dict(ups=updates / dt, sec=dt, K=K)
+
+
 def family_bench(fdw, torch, I, steps, warmup, persistent=False):
     fam = I.family()
     s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
@@ -345,6 +414,8 @@ def main():
     log(json.dumps(f32))
     nodes = f32["n"] * f32["n"]
     K = f32["K"]
+    copy_GBs = copy_bench(torch)
+    log("device-to-device copy", round(copy_GBs, 1), "GB/s")
     per_launch_bytes = 5 * 4 * nodes  # read u, du, h; write u, du (FP32 words) per streaming launch
     avg_launch_s = f32["kernel_ms"] / 1e3 / max(f32["launches"], 1)
     achieved = per_launch_bytes / avg_launch_s / 1e9
@@ -361,7 +432,11 @@ def main():
         "launches": f32["launches"],
         "bytes_per_launch": per_launch_bytes,
         "effective_vs_single_step_roofline": round(f32["ups"] / (HBM_PEAK_GBS * 1e9 / 20.0), 3),
+        "d2d_copy_GBs": round(copy_GBs, 1),
     }
+    if traffic:
+        roof["traffic_GBs"] = round(traffic / avg_launch_s / 1e9, 1)
+        roof["traffic_vs_copy"] = round(traffic / avg_launch_s / 1e9 / copy_GBs, 4)
     out = {
         "metric": METRIC,
         "value": round(f32["ups"], 1),
@@ -423,6 +498,20 @@ def main():
                                       "/ forward solve; ratio_recorded: adjoint call from checkpoints stored by the "
                                       "forward solve / forward solve; gradient_ratio: (forward solve storing "
                                       "checkpoints + adjoint from them) / forward solve"}
+    if not args.skip_extra:
+        torch.cuda.empty_cache()
+        log("small 256^2 fp64 line")
+        sm = small_bench(fdw, torch, I, args.steps)
+        out["small"] = {"us_per_step": round(sm["us_per_step"], 3), "time_block": sm["K"],
+                        "workload": "256x256 FP64 line singularity h = 1 + 2 phi_0.05(x), 1000 steps with per-step "
+                                    "energy, launch sequence replayed from a hipGraph (cache-resident)"}
+        log("largest 16384^2 fp32")
+        lg = largest_bench(fdw, torch, I, max(1, args.steps - 2))
+        out["largest"] = {"value": round(lg["ups"], 1), "unit": "grid-point updates/s",
+                          "ms_per_step": round(lg["sec"] * 1e3, 2), "time_block": lg["K"],
+                          "workload": "16384x16384 FP32 smooth random bathymetry 0.2-1 + delta ridge eps = 2 dx, "
+                                      "10000 steps, no energy"}
+        torch.cuda.empty_cache()
     if not args.skip_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(I)

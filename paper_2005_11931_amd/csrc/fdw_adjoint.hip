@@ -41,8 +41,11 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
 {
     constexpr int Hx = ((K + C - 1) / C) * C;
     constexpr int Wv = kWaveSize * C - 2 * Hx;
-    constexpr int U = RowUnroll<K>::U;
-    constexpr int NB = RowUnroll<K>::NB;
+    // rows are loaded one row ahead: this kernel holds twice the forward's registers, and a
+    // deeper prefetch buys nothing measurable at two waves per SIMD while pushing the FP32
+    // variants to one wave
+    constexpr int NB = 2;
+    constexpr int U = (K % 2 == 0) ? K : 2 * K;
     static_assert(U % NB == 0 && U % K == 0 && U % 2 == 0, "row unroll");
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();

@@ -159,7 +159,7 @@ size_t header_bytes(int count)
     size_t b = align_up(sizeof(MemberDev) * (size_t)count, kAlign);
     b += align_up(sizeof(double) * (4 * kRedBlocks + 16), kAlign);  // red
     b += align_up(sizeof(int) * 16, kAlign);                         // status
-    b += align_up(sizeof(int) * 16, kAlign);                         // barrier
+    b += align_up(sizeof(int) * kPersistentCtlInts, kAlign);         // persistent launch control
     b += align_up(sizeof(double) * (size_t)std::max(count, 1) * 2, kAlign);  // scalars
     return b;
 }
@@ -478,8 +478,10 @@ int run_persistent(fdw_ctx* c, int64_t steps)
     for (const MemberDev& md : c->tab) total += md.blocks;
     int grid = std::min(total, persistent_max_blocks<T>(K, c->C, face_mode));
     if (grid < 1) return fail(c, FDW_EHIP, "persistent launch: no resident blocks");
-    if (phases > 0) {
-        HIPCHK(c, launch_fill_bytes(c->barrier, 16 * sizeof(int), c->stream));
+    for (int64_t done = 0; done < phases;) {
+        // one cooperative launch per kPersistentPhases time blocks
+        const int ph = (int)std::min<int64_t>(kPersistentPhases, phases - done);
+        HIPCHK(c, launch_fill_bytes(c->barrier, (size_t)(16 + 8 * ph) * sizeof(int), c->stream));
         StepArgs a;
         a.table = c->tab_dev;
         a.first = 0;
@@ -490,14 +492,14 @@ int run_persistent(fdw_ctx* c, int64_t steps)
         a.want_energy = 0;
         a.want_trace = 0;
         a.ctx_step = c->ctx_step;
-        if (phases > INT32_MAX) return fail(c, FDW_EINVAL, "too many steps for one persistent launch");
-        HIPCHK(c, launch_step_persistent<T>(a, K, c->C, face_mode, (int)phases, grid, c->barrier, c->stream));
-        c->ctx_step += phases * K;
-        c->launches += phases;
+        HIPCHK(c, launch_step_persistent<T>(a, K, c->C, face_mode, ph, grid, c->barrier, c->stream));
+        c->ctx_step += (int64_t)ph * K;
+        c->launches += ph;
         for (HostMember& hm : c->m) {
-            hm.n += phases * K;
-            if (phases & 1) hm.cur ^= 1;
+            hm.n += (int64_t)ph * K;
+            if (ph & 1) hm.cur ^= 1;
         }
+        done += ph;
     }
     if (tail > 0) return run_blocks<T>(c, tail, nullptr, 0, 0, c->stream);
     return FDW_OK;
@@ -657,7 +659,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
     c->tab_dev = (MemberDev*)take(sizeof(MemberDev) * (size_t)count);
     c->red = (double*)take(sizeof(double) * (4 * kRedBlocks + 16));
     c->status = (int*)take(sizeof(int) * 16);
-    c->barrier = (int*)take(sizeof(int) * 16);
+    c->barrier = (int*)take(sizeof(int) * kPersistentCtlInts);
     c->scal = (double*)take(sizeof(double) * (size_t)std::max(count, 1) * 2);
     c->m.resize(count);
     c->tab.resize(count);

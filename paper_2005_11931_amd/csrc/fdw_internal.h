@@ -16,6 +16,10 @@ constexpr int kWaveSize = 64;         // CDNA wavefront
 constexpr int kWavesPerBlock = 4;     // independent streaming waves per workgroup
 constexpr int kMaxReceivers = 16384;  // per member
 constexpr int kRedBlocks = 1024;      // blocks of the generic two-stage reductions
+// persistent batched launch: at most this many time blocks per launch; its control words are
+// the grid barrier (16 ints) and one work counter per (time block, XCD)
+constexpr int kPersistentPhases = 1024;
+constexpr int kPersistentCtlInts = 16 + 8 * kPersistentPhases;
 constexpr int kPadRowsTop = 0;        // rows reserved above / below each plane (none needed: the
 constexpr int kPadRowsBottom = 0;     // streaming kernel's buffer loads return 0 outside the grid)
 

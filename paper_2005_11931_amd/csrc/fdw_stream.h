@@ -507,10 +507,12 @@ static hipError_t launch_step_c(const StepArgs& a, int K, int face_mode, int gri
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
 {
-    // every wave publishes its own stores before the block arrives ...
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // The block's stores reach its L2 by the workgroup barrier; one agent-scope release by
+    // the arriving thread then writes that L2 back for the other XCDs (the L2 write-back and
+    // invalidate act on the whole cache, so one per block is enough) ...
     __syncthreads();
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -526,23 +528,38 @@ __device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
             }
         }
     }
+    // ... and its acquire invalidates this CU's L1 and the XCD's L2 before any wave of the
+    // block reads the other blocks' results
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     gen += 1;
     __syncthreads();
-    // ... and every wave sees the other blocks' stores afterwards
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <typename T, int K, int C, int FACE>
 __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar)
 {
     const int total_waves = a.total_blocks * kWavesPerBlock;  // work items of one time block
-    const int gw0 = blockIdx.x * kWavesPerBlock + wave_in_block();
-    const int stride = gridDim.x * kWavesPerBlock;
+    // Workgroups land on the 8 XCDs round-robin (block b on XCD b mod 8).  Each XCD takes a
+    // contiguous eighth of the work items, so that neighbouring strips and segments (which
+    // share halo rows and columns) go through the same L2; within it, waves take items one at
+    // a time from a per-(time block, XCD) counter, which balances uneven items.  With fewer
+    // than 8 blocks there is one range and one counter.
+    const bool by_xcd = gridDim.x >= 8;
+    const int xcd = by_xcd ? (int)(blockIdx.x & 7) : 0;
+    const int lo = by_xcd ? (int)((int64_t)total_waves * xcd / 8) : 0;
+    const int hi = by_xcd ? (int)((int64_t)total_waves * (xcd + 1) / 8) : total_waves;
+    const int lane = threadIdx.x & 63;
+    int* const counters = bar + 16;
     int gen = 0;
     int parity = a.parity;
     int64_t step = a.ctx_step;
     for (int p = 0; p < phases; ++p) {
-        for (int item = gw0; item < total_waves; item += stride) {
+        for (;;) {
+            int k = 0;
+            if (lane == 0) k = __hip_atomic_fetch_add(&counters[8 * p + xcd], 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            const int item = lo + __builtin_amdgcn_readfirstlane(k);
+            if (item >= hi) break;
             const int gb = item / kWavesPerBlock + a.block_offset;
             const int m = find_member(a.table, a.first, a.nmembers, gb);
             const MemberDev& M = a.table[m];
