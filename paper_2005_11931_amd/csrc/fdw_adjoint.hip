@@ -294,10 +294,17 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     T uo[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) uo[c] = Ur[t][pr][c];
-                    store_pack<T, C>(uout + off, uo);
-                    store_pack<T, C>(dout + off, nd);
-                    store_pack<T, C>(lout + off, nl);
-                    store_pack<T, C>(mout + off, nm);
+                    if (a.stream_nt) {
+                        store_row_nt<T, C>(uout + off, uo);
+                        store_row_nt<T, C>(dout + off, nd);
+                        store_row_nt<T, C>(lout + off, nl);
+                        store_row_nt<T, C>(mout + off, nm);
+                    } else {
+                        store_pack<T, C>(uout + off, uo);
+                        store_pack<T, C>(dout + off, nd);
+                        store_pack<T, C>(lout + off, nl);
+                        store_pack<T, C>(mout + off, nm);
+                    }
                 }
             }
             // the row at position p-K has all K contributions (ring index (p-K) mod K = s mod K)
@@ -312,8 +319,13 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                         o1[c] = gbuf[pb][c] + GX[qd][c];
                         o2[c] = g2buf[pb][c] + GY[qd][c];
                     }
-                    store_pack<double, C>(a.g1 + off, o1);
-                    if (split) store_pack<double, C>(a.g2 + off, o2);
+                    if (a.stream_nt) {
+                        store_row_nt<double, C>(a.g1 + off, o1);
+                        if (split) store_row_nt<double, C>(a.g2 + off, o2);
+                    } else {
+                        store_pack<double, C>(a.g1 + off, o1);
+                        if (split) store_pack<double, C>(a.g2 + off, o2);
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < C; ++c) GX[qd][c] = GY[qd][c] = 0.0;

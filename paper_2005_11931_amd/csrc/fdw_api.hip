@@ -227,10 +227,23 @@ int layout_for_K(fdw_ctx* c, int K, int S, hipStream_t st = nullptr)
     return FDW_OK;
 }
 
+// Non-temporal streaming pays off once a member's planes (state in and out, coefficients)
+// are well beyond the last-level cache; below that (a 2048^2 FP64 solve, the 4096^2 FP32
+// members of a family) normal accesses keep part of the set cached from one launch to the
+// next and measure faster.
+bool stream_nt(const fdw_ctx* c)
+{
+    size_t b = 0;
+    for (const HostMember& hm : c->m)
+        b = std::max(b, (size_t)(hm.face ? 6 : 5) * hm.ld * hm.ny * elem_size(c->dtype));
+    return b > 2 * kLastLevelCacheBytes;
+}
+
 void sync_member_dev(fdw_ctx* c, int i)
 {
     HostMember& hm = c->m[i];
     MemberDev& md = c->tab[i];
+    md.stream_nt = stream_nt(c) ? 1 : 0;
     md.cur0 = hm.cur ^ (int)(c->launches & 1);
     md.n_offset = hm.n - c->ctx_step;
     md.face = hm.face;
@@ -385,6 +398,7 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
     a.want_energy = energy ? 1 : 0;
     a.want_trace = trace ? 1 : 0;
     a.ctx_step = c->ctx_step;
+    a.stream_nt = stream_nt(c) ? 1 : 0;
     int face_mode = c->m[first].face;
     for (int i = first; i < first + nm; ++i)
         if (c->m[i].face != face_mode) face_mode = -1;
@@ -492,6 +506,7 @@ int run_persistent(fdw_ctx* c, int64_t steps)
         a.want_energy = 0;
         a.want_trace = 0;
         a.ctx_step = c->ctx_step;
+        a.stream_nt = stream_nt(c) ? 1 : 0;
         HIPCHK(c, launch_step_persistent<T>(a, K, c->C, face_mode, ph, grid, c->barrier, c->stream));
         c->ctx_step += (int64_t)ph * K;
         c->launches += ph;
@@ -1177,6 +1192,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
             a.want_energy = 0;
             a.want_trace = 0;
             a.ctx_step = 0;
+            a.stream_nt = rep.stream_nt;
             HIPCHK(c, launch_step<T>(a, Kb, c->C, hm.face, rep.blocks, s));
             cur ^= 1;
             n += Kb;
@@ -1204,6 +1220,9 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     A.g2 = g2_out ? G2 : G1;
     A.R = R;
     A.trace_grad = tg;
+    // reverse launch: u, du, lam, mu in and out, h (and hy), the FP64 accumulator in and out
+    A.stream_nt = ((size_t)(hm.face ? 10 : 9) * elem_size(c->dtype) + 2 * sizeof(double)) * hm.ld * hm.ny >
+                  2 * kLastLevelCacheBytes ? 1 : 0;
     // seed lam^N = mu^N = s_N (planes are zero)
     A.lout = LA[0];
     A.mout = MU[0];

@@ -19,6 +19,8 @@ constexpr int kRedBlocks = 1024;      // blocks of the generic two-stage reducti
 // persistent batched launch: at most this many time blocks per launch; its control words are
 // the grid barrier (16 ints) and one work counter per (time block, XCD)
 constexpr int kPersistentPhases = 1024;
+// last-level (Infinity) cache of the MI355X; working sets above it are streamed non-temporally
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
 constexpr int kPersistentCtlInts = 16 + 8 * kPersistentPhases;
 constexpr int kPadRowsTop = 0;        // rows reserved above / below each plane (none needed: the
 constexpr int kPadRowsBottom = 0;     // streaming kernel's buffer loads return 0 outside the grid)
@@ -49,7 +51,8 @@ struct MemberDev {
     void* traces;           // [trace_rows][R]
     double* epart;          // energy partials [kMaxTimeBlock][max waves]
     int epart_stride;       // max waves
-    int pad_;
+    int stream_nt;          // 1: the launch's planes exceed the last-level cache; stream them
+                            // with non-temporal accesses (0: keep them cacheable)
 };
 
 // Per-launch arguments of the streaming stencil.
@@ -63,6 +66,8 @@ struct StepArgs {
     int want_energy;
     int want_trace;
     int64_t ctx_step;  // context step before this launch
+    int stream_nt;     // 1: the launch's working set exceeds the last-level cache (see MemberDev)
+    int pad_;
 };
 
 // ---- launchers (fdw_kernels.hip) ---------------------------------------------------------
@@ -128,6 +133,7 @@ struct AdjArgs {
     const double* trace_grad;  // [N+1][R]
     int64_t n_top;             // forward step index of the input state u (level n_top)
     int strips, segs, seg_rows, waves;
+    int stream_nt;             // 1: write the outputs with non-temporal stores (planes exceed the cache)
 };
 template <typename T>
 hipError_t launch_adjoint_block(const AdjArgs& a, int K, int C, int grid, hipStream_t s);

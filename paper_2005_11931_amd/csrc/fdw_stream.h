@@ -176,34 +176,60 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, u
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferWord3);
 }
 
-// Loads the whole C-element vector; every element is consumed by the caller.
-template <typename T, int C>
+// Loads the whole C-element vector; every element is consumed by the caller.  AUX: cache
+// policy bits of the load (2 = non-temporal).
+template <typename T, int C, int AUX = 0>
 __device__ __forceinline__ void buffer_row(__amdgpu_buffer_rsrc_t r, unsigned int off, T (&out)[C])
 {
     static_assert(sizeof(T) * C == 32 || sizeof(T) * C == 16 || sizeof(T) * C == 8, "8/16/32-byte lane vectors");
     Pack<T, C> q;
     if constexpr (sizeof(T) * C == 32) {
-        const fdw_u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
-        const fdw_u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + 16u), 0, 0);
+        const fdw_u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
+        const fdw_u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + 16u), 0, AUX);
         const fdw_u32x8 v = {v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
         q = __builtin_bit_cast(Pack<T, C>, v);
     } else if constexpr (sizeof(T) * C == 16) {
-        const fdw_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        const fdw_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
         q = __builtin_bit_cast(Pack<T, C>, v);
     } else {
-        const fdw_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        const fdw_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX);
         q = __builtin_bit_cast(Pack<T, C>, v);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) out[c] = q.v[c];
 }
 
-// MODE bit 0: per-step energy partials; bit 1: receiver traces.
+// Non-temporal row stores, for working sets larger than the caches: the next launch reads the
+// rows back from HBM anyway, and keeping them out of L2 leaves room for the halo rows that
+// neighbouring work items share.
+template <typename T, int C>
+__device__ __forceinline__ void store_row_nt(T* __restrict__ p, const T (&in)[C])
+{
+    constexpr int B = (int)sizeof(T) * C;
+    static_assert(B == 8 || B == 16 || B == 32, "8-, 16- or 32-byte rows per lane");
+    Pack<T, C> q;
+#pragma unroll
+    for (int c = 0; c < C; ++c) q.v[c] = in[c];
+    if constexpr (B == 8) {
+        __builtin_nontemporal_store(__builtin_bit_cast(fdw_u32x2, q), reinterpret_cast<fdw_u32x2*>(p));
+    } else if constexpr (B == 16) {
+        __builtin_nontemporal_store(__builtin_bit_cast(fdw_u32x4, q), reinterpret_cast<fdw_u32x4*>(p));
+    } else {
+        const fdw_u32x8 v = __builtin_bit_cast(fdw_u32x8, q);
+        const fdw_u32x4 lo = {v[0], v[1], v[2], v[3]}, hi = {v[4], v[5], v[6], v[7]};
+        __builtin_nontemporal_store(lo, reinterpret_cast<fdw_u32x4*>(p));
+        __builtin_nontemporal_store(hi, reinterpret_cast<fdw_u32x4*>(p) + 1);
+    }
+}
+
+// MODE bit 0: per-step energy partials; bit 1: receiver traces; bit 2: non-temporal loads of
+// the state rows (FP32 launches whose working set exceeds the last-level cache).
 template <typename T, int K, int C, int FACE, int MODE>
 __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step)
 {
     constexpr bool want_energy = (MODE & 1) != 0;
     constexpr bool want_trace = (MODE & 2) != 0;
+    constexpr bool nt_loads = (MODE & 4) != 0;
     constexpr int Hx = ((K + C - 1) / C) * C;   // halo columns on each side (multiple of C)
     constexpr int Wv = kWaveSize * C - 2 * Hx;  // owned columns per strip
     constexpr int U = RowUnroll<K>::U;
@@ -282,11 +308,17 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     // grid load as zeros and are never stored).
     const int nblk = (r1 - r0 + 2 * K + U - 1) / U;
     const size_t lane_off = (size_t)(ptrdiff_t)cb;
+    // Working sets above the last-level cache are streamed: outputs with non-temporal stores,
+    // and in FP32 the state rows with non-temporal loads (MODE bit 2: measured faster there,
+    // slower in FP64).  Sets that fit keep normal accesses, so that the next launch finds them
+    // cached.
+    const bool nt = M.stream_nt != 0;
+    constexpr int kStatePolicy = nt_loads ? 2 : 0;
     auto load_row = [&](int p, T (&u)[C], T (&d)[C], T (&h)[C], T (&hy)[C]) {
         const int j = rfirst + dir * p;
         const unsigned int off = (j < jbase) ? kBufferOutOfRange : (unsigned int)(j - jbase) * row_bytes + lane_col;
-        buffer_row<T, C>(ru, off, u);
-        buffer_row<T, C>(rd, off, d);
+        buffer_row<T, C, kStatePolicy>(ru, off, u);
+        buffer_row<T, C, kStatePolicy>(rd, off, d);
         buffer_row<T, C>(rh, off, h);
         if (FACE) buffer_row<T, C>(rhy, off, hy);
     };
@@ -420,8 +452,13 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
                     }
                 } else if (rown && lane_owned) {
                     const size_t off = (size_t)(ptrdiff_t)r * ld + lane_off;
-                    store_pack<T, C>(uout + off, nu);
-                    store_pack<T, C>(dout + off, nd);
+                    if (nt) {
+                        store_row_nt<T, C>(uout + off, nu);
+                        store_row_nt<T, C>(dout + off, nd);
+                    } else {
+                        store_pack<T, C>(uout + off, nu);
+                        store_pack<T, C>(dout + off, nd);
+                    }
                 }
             }
             // keep the scheduler from interleaving consecutive rows (bounds register pressure)
@@ -465,14 +502,24 @@ template <typename T, int K, int C, int FACE>
 static hipError_t launch_step_kcf(const StepArgs& a, int grid, hipStream_t s)
 {
     const dim3 g(grid), b(kWaveSize * kWavesPerBlock);
-    if (a.want_energy && a.want_trace)
-        hipLaunchKernelGGL((k_step<T, K, C, FACE, 3>), g, b, 0, s, a);
-    else if (a.want_energy)
-        hipLaunchKernelGGL((k_step<T, K, C, FACE, 1>), g, b, 0, s, a);
-    else if (a.want_trace)
-        hipLaunchKernelGGL((k_step<T, K, C, FACE, 2>), g, b, 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step<T, K, C, FACE, 0>), g, b, 0, s, a);
+    const int mode = (a.want_energy ? 1 : 0) | (a.want_trace ? 2 : 0);
+    if constexpr (sizeof(T) == 4) {
+        if (a.stream_nt) {
+            switch (mode) {
+            case 3: hipLaunchKernelGGL((k_step<T, K, C, FACE, 7>), g, b, 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_step<T, K, C, FACE, 5>), g, b, 0, s, a); break;
+            case 2: hipLaunchKernelGGL((k_step<T, K, C, FACE, 6>), g, b, 0, s, a); break;
+            default: hipLaunchKernelGGL((k_step<T, K, C, FACE, 4>), g, b, 0, s, a); break;
+            }
+            return hipGetLastError();
+        }
+    }
+    switch (mode) {
+    case 3: hipLaunchKernelGGL((k_step<T, K, C, FACE, 3>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_step<T, K, C, FACE, 1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_step<T, K, C, FACE, 2>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_step<T, K, C, FACE, 0>), g, b, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
