@@ -197,7 +197,8 @@ int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
 /* Autotune the execution configuration for this context: times short runs of the candidate
  * (columns per lane, time block, segment rows) triples on the context's stream, picks the
  * fastest (a larger time block must win by 2%) and applies it.  Every member must be at
- * step 0 (FDW_ESTATE otherwise) and is returned to step 0.  The choice is cached in the
+ * step 0 (FDW_ESTATE otherwise) and is returned to step 0 (a checkpoint recording stops).
+ * The choice is cached in the
  * file named by the FDW_AUTOTUNE_CACHE environment variable (if set) under a key of
  * (device arch, storage type, member sizes and layouts).  steps: time steps per candidate
  * run (0 = automatic).  best_out (host, may be NULL) receives

@@ -1381,6 +1381,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
         if (hm.n != 0) return fail(c, FDW_ESTATE, "autotune runs from step 0 (call fdw_reset first)");
     }
+    c->rec.member = -1;  // the candidate runs overwrite any checkpoint recording
     const std::string key = tune_key(c);
     int bestK = 0, bestS = 0, bestC_out = c->C;
     if (!cache_lookup(key, &bestK, &bestS, &bestC_out)) {

@@ -1,0 +1,71 @@
+"""The autotuner (fdw_autotune): it picks a supported (time block, segment rows, lane columns)
+configuration for a batched context, caches it under the context's key, and the results it
+leads to equal those of the default configuration bit for bit (the launch configuration never
+changes the arithmetic)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2005_11931_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    out = []
+    for k, (nx, ny) in enumerate([(300, 200), (512, 384), (257, 257)]):
+        rng = np.random.default_rng(700 + k)
+        x, y, X, Y = I.mesh(nx, ny)
+        h = 1.0 + 2.0 * I.gaussian_1d(X, 0.05) + 0.2 * rng.uniform(size=(ny, nx))
+        u0 = I.zero_ring(np.exp(-((X - 0.3) ** 2 + (Y + 0.1) ** 2) / 0.01))
+        dx, dy = 2.0 / (nx - 1), 2.0 / (ny - 1)
+        tau = 0.45 / np.sqrt(h.max() * (1 / dx**2 + 1 / dy**2))
+        out.append(I.Case(f"tune{k}", nx, ny, -1, 1, -1, 1, tau, 200, h, None, u0, np.zeros_like(u0)))
+    # one time step for all members (the family advances in lock-step)
+    tau = min(c.tau for c in out)
+    return [I.Case(**{**c.__dict__, "tau": tau}) for c in out]
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "f64"])
+def test_autotune_choice_cache_and_bitwise_results(tmp_path, dtype_name):
+    import torch
+
+    from paper_2005_11931_amd import fdw
+
+    dt = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
+    cases = _cases()
+    cache = tmp_path / "tune.txt"
+    os.environ["FDW_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        print("autotune", dtype_name, flush=True)
+        s = fdw.family_solver(cases, dtype=dt)
+        K, S, C = s.autotune(steps=32)
+        assert (K, S, C) == (s.config(fdw.FDW_CFG_TIME_BLOCK), s.config(fdw.FDW_CFG_SEGMENT_ROWS),
+                             s.config(fdw.FDW_CFG_LANE_COLUMNS))
+        if dt == fdw.FDW_F32:
+            assert (C == 2 and 1 <= K <= 8) or (C == 4 and 1 <= K <= 6)
+        else:
+            assert C == 2 and 1 <= K <= 4
+        assert S in (16, 32, 64, 128)
+        assert all(s.steps_taken(m) == 0 for m in range(len(cases)))
+        text = cache.read_text()
+        assert text.count("|") == 1 and text.strip().endswith(f"{K} {S} {C}")
+        e = s.step(150, energy=True).cpu().numpy()
+        tuned = [s.get_state(m)[0].cpu().numpy() for m in range(len(cases))]
+        s.close()
+        # a second context of the same shape takes the cached choice
+        s2 = fdw.family_solver(cases, dtype=dt)
+        assert s2.autotune(steps=32) == (K, S, C)
+        s2.close()
+        assert cache.read_text() == text
+        # the default configuration gives the same numbers, bit for bit
+        s3 = fdw.family_solver(cases, dtype=dt)
+        e3 = s3.step(150, energy=True).cpu().numpy()
+        for m in range(len(cases)):
+            assert np.array_equal(tuned[m], s3.get_state(m)[0].cpu().numpy()), m
+        tol = 1e-13 if dt == fdw.FDW_F64 else 1e-6
+        assert np.abs(e - e3).max() <= tol * np.abs(e3).max()
+        s3.close()
+    finally:
+        del os.environ["FDW_AUTOTUNE_CACHE"]
