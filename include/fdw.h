@@ -172,8 +172,8 @@ int fdw_reset(fdw_ctx* ctx, int32_t member);
 int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
 
 /* Execution configuration (tuning; results do not depend on it, bit for bit):
- *   FDW_CFG_TIME_BLOCK: time steps per stencil launch: 1..8 for float with 2 columns per lane, 1..6
- *     with 4, 1..4 for double (0 = automatic);
+ *   FDW_CFG_TIME_BLOCK: time steps per stencil launch: 1..8 for float with 2 columns per lane and
+ *     double with 1, 1..6 for float with 4, 1..4 for double with 2 (0 = automatic);
  *   FDW_CFG_SEGMENT_ROWS: rows per streaming work item, 8..4096 (0 = automatic);
  *   FDW_CFG_USE_GRAPH: 1 captures the launch sequence of a step_n call in a hipGraph and
  *     replays it for later calls with the same shape (0 = plain launches);
@@ -185,7 +185,8 @@ enum {
     FDW_CFG_USE_GRAPH = 3,
     FDW_CFG_BATCH_MODE = 4,
     FDW_CFG_TIMING = 5, /* 1: bracket every stencil launch with HIP events (see fdw_kernel_time) */
-    FDW_CFG_LANE_COLUMNS = 6, /* grid columns per lane of the streaming kernels: 2 or 4 (float), 2 (double); 0 = default */
+    FDW_CFG_LANE_COLUMNS = 6, /* grid columns per lane of the streaming kernels: 2 or 4 (float), 1 or 2
+                                 (double); 0 = default */
     FDW_CFG_ADJ_TIME_BLOCK = 7,  /* reverse steps per launch of the adjoint sweep, 1..4 (0 = 4) */
     FDW_CFG_ADJ_LANE_COLUMNS = 8, /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
                                      0 = default (2 for float, 1 for double) */

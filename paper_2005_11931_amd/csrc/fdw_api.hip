@@ -26,7 +26,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-inline int default_cols_per_lane(int dtype) { return dtype == FDW_F32 ? 2 : 2; }
+// one 8-byte value per lane and row: FP32 pairs, FP64 singles (the deepest time blocks fit)
+inline int default_cols_per_lane(int dtype) { return dtype == FDW_F32 ? 2 : 1; }
 // every plane carries zero rows above and below the grid (streamed rows may run past it)
 inline size_t plane_alloc(int ld, int ny, size_t es)
 {
@@ -132,14 +133,17 @@ bool problem_ok(const fdw_problem& p, std::string* why, int64_t* N_out)
     return true;
 }
 
-int max_strips(int nx)
+// column strips of a streaming launch with C columns per lane and time block K
+int strips_for(int nx, int C, int K)
 {
-    // narrowest strip: 2 columns per lane, 8-step time block
-    const int C = 2;
-    const int Hx = ((kMaxTimeBlock + C - 1) / C) * C;
+    const int Hx = ((K + C - 1) / C) * C;
     const int Wv = kWaveSize * C - 2 * Hx;
     return (nx + Wv - 1) / Wv;
 }
+
+// upper bound over every configuration (sizes the per-wave buffers): the narrowest strip has
+// 1 column per lane and the deepest time block
+int max_strips(int nx) { return strips_for(nx, 1, kMaxTimeBlock); }
 
 size_t member_bytes(const fdw_problem& p)
 {
@@ -179,8 +183,9 @@ void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int
 int choose_K(const fdw_ctx* c)
 {
     if (c->K_cfg > 0) return c->K_cfg;
-    // deepest time block that keeps three waves per SIMD (2 columns per lane)
-    return c->dtype == FDW_F32 ? (c->C == 4 ? 6 : 8) : 4;
+    // deepest time block of the configuration (8 with one 8-byte value per lane and row)
+    if (c->dtype == FDW_F32) return c->C == 4 ? 6 : 8;
+    return c->C == 1 ? 8 : 4;
 }
 
 int choose_S(const fdw_ctx* c)
@@ -193,7 +198,7 @@ int choose_S(const fdw_ctx* c)
     const int K = choose_K(c);
     int best = kMinSegRows;
     for (const HostMember& hm : c->m) {
-        const int64_t strips = max_strips(hm.nx);
+        const int64_t strips = strips_for(hm.nx, c->C, K);
         int64_t S = (hm.ny * strips + 4607) / 4608;
         S = std::min<int64_t>(16 * K, std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8));
         best = std::max(best, (int)S);
@@ -981,9 +986,9 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
     if (!c) return FDW_EINVAL;
     switch (key) {
     case FDW_CFG_TIME_BLOCK:
-        if (v < 0 || v > kMaxTimeBlock || (c->dtype == FDW_F64 && v > 4) || (c->C == 4 && v > 6))
-            return fail(c, FDW_EINVAL, "time block must be 0..8 (float, 2 columns per lane), 0..6 (float, 4 columns) "
-                                       "or 0..4 (double)");
+        if (v < 0 || v > kMaxTimeBlock || (c->dtype == FDW_F64 && c->C == 2 && v > 4) || (c->C == 4 && v > 6))
+            return fail(c, FDW_EINVAL, "time block must be 0..8 (float with 2 columns per lane, double with 1), "
+                                       "0..6 (float, 4 columns) or 0..4 (double, 2 columns)");
         c->K_cfg = (int)v;
         break;
     case FDW_CFG_SEGMENT_ROWS:
@@ -1005,9 +1010,11 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         break;
     case FDW_CFG_LANE_COLUMNS:
         if (v == 0) v = default_cols_per_lane(c->dtype);
-        if (!(v == 2 || (v == 4 && c->dtype == FDW_F32)))
-            return fail(c, FDW_EINVAL, "lane columns must be 2 or 4 (float) / 2 (double)");
+        if (!(v == 2 || (v == 4 && c->dtype == FDW_F32) || (v == 1 && c->dtype == FDW_F64)))
+            return fail(c, FDW_EINVAL, "lane columns must be 2 or 4 (float) / 1 or 2 (double)");
         if (v == 4 && c->K_cfg > 6) return fail(c, FDW_EINVAL, "4 columns per lane supports time blocks up to 6");
+        if (v == 2 && c->dtype == FDW_F64 && c->K_cfg > 4)
+            return fail(c, FDW_EINVAL, "double with 2 columns per lane supports time blocks up to 4");
         c->C = (int)v;
         break;
     case FDW_CFG_ADJ_TIME_BLOCK:
@@ -1400,6 +1407,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
             for (int K = 1; K <= 6; ++K) CK.push_back({4, K});
         } else {
             for (int K = 1; K <= 4; ++K) CK.push_back({2, K});
+            for (int K = 1; K <= 8; ++K) CK.push_back({1, K});
         }
         const int Ss[] = {16, 32, 64, 128};
         const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode, saveC = c->C;

@@ -31,15 +31,19 @@ namespace fdw {
 hipError_t launch_step_f32c4(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
 hipError_t launch_step_f32c2(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
 hipError_t launch_step_f64c2(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
+hipError_t launch_step_f64c1(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
 hipError_t launch_persistent_f32c4(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
                                    hipStream_t s);
 hipError_t launch_persistent_f32c2(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
                                    hipStream_t s);
 hipError_t launch_persistent_f64c2(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
                                    hipStream_t s);
+hipError_t launch_persistent_f64c1(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                   hipStream_t s);
 int persistent_max_f32c4(int K, int face_mode);
 int persistent_max_f32c2(int K, int face_mode);
 int persistent_max_f64c2(int K, int face_mode);
+int persistent_max_f64c1(int K, int face_mode);
 
 template <>
 hipError_t launch_step<float>(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s)
@@ -52,6 +56,7 @@ template <>
 hipError_t launch_step<double>(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s)
 {
     if (C == 2) return launch_step_f64c2(a, K, face_mode, grid, s);
+    if (C == 1) return launch_step_f64c1(a, K, face_mode, grid, s);
     return hipErrorInvalidValue;
 }
 template <>
@@ -67,6 +72,7 @@ hipError_t launch_step_persistent<double>(const StepArgs& a, int K, int C, int f
                                           int* bar, hipStream_t s)
 {
     if (C == 2) return launch_persistent_f64c2(a, K, face_mode, phases, grid, bar, s);
+    if (C == 1) return launch_persistent_f64c1(a, K, face_mode, phases, grid, bar, s);
     return hipErrorInvalidValue;
 }
 template <>
@@ -80,6 +86,7 @@ template <>
 int persistent_max_blocks<double>(int K, int C, int face_mode)
 {
     if (C == 2) return persistent_max_f64c2(K, face_mode);
+    if (C == 1) return persistent_max_f64c1(K, face_mode);
     return 0;
 }
 

@@ -1,0 +1,19 @@
+// fdw_step_f64c1.hip - instantiation unit of the streaming stencil: double storage, 1 grid
+// column per lane (one 8-byte value per lane and row, like FP32 with 2 columns), time blocks
+// K = 1..8.
+#include "fdw_stream.h"
+
+namespace fdw {
+
+hipError_t launch_step_f64c1(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s)
+{
+    return launch_step_c<double, 1, 8>(a, K, face_mode, grid, s);
+}
+hipError_t launch_persistent_f64c1(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
+                                   hipStream_t s)
+{
+    return launch_persistent_c<double, 1, 8>(a, K, face_mode, phases, grid, bar, s);
+}
+int persistent_max_f64c1(int K, int face_mode) { return persistent_max_c<double, 1, 8>(K, face_mode); }
+
+}  // namespace fdw

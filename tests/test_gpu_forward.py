@@ -136,9 +136,10 @@ def test_variants_bitwise(dtype_name, layout):
     case = I.Case("var", nx, ny, -1, 1, -1, 1, tau, N, h1, h2, u0, u1)
     dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
     base = None
-    Cs = (2, 4) if dt == fdw.FDW_F32 else (2,)
+    Cs = (2, 4) if dt == fdw.FDW_F32 else (2, 1)
     for C in Cs:
-        Ks = (1, 2, 3, 4, 5, 6, 7, 8) if (dt == fdw.FDW_F32 and C == 2) else ((1, 2, 3, 4, 5, 6) if C == 4 else (1, 2, 3, 4))
+        deep = C == 1 or (dt == fdw.FDW_F32 and C == 2)
+        Ks = (1, 2, 3, 4, 5, 6, 7, 8) if deep else ((1, 2, 3, 4, 5, 6) if C == 4 else (1, 2, 3, 4))
         for K in Ks:
             for S in (16, 48, 1024):
                 _say("variant", dtype_name, layout, C, K, S)

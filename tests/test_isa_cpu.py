@@ -15,7 +15,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2005_11931_amd", "csrc")
-UNITS = ["fdw_step_f32c2.hip", "fdw_step_f32c4.hip", "fdw_step_f64c2.hip", "fdw_adjoint.hip", "fdw_kernels.hip"]
+UNITS = ["fdw_step_f32c2.hip", "fdw_step_f32c4.hip", "fdw_step_f64c2.hip", "fdw_step_f64c1.hip",
+         "fdw_adjoint.hip", "fdw_kernels.hip"]
 
 
 def _asm(unit, tmp):
@@ -51,7 +52,7 @@ def _meta(text, name):
 @pytest.mark.slow
 def test_buffer_loads_have_lane_vector_width(asm):
     expect = {"fdw_step_f32c2.hip": {"buffer_load_dwordx2"}, "fdw_step_f32c4.hip": {"buffer_load_dwordx4"},
-              "fdw_step_f64c2.hip": {"buffer_load_dwordx4"}}
+              "fdw_step_f64c2.hip": {"buffer_load_dwordx4"}, "fdw_step_f64c1.hip": {"buffer_load_dwordx2"}}
     for unit, widths in expect.items():
         funcs = _functions(asm[unit])
         assert funcs, unit
@@ -70,8 +71,8 @@ def test_buffer_loads_have_lane_vector_width(asm):
 
 @pytest.mark.slow
 def test_default_stream_variants_do_not_spill(asm):
-    # float: 2 columns per lane, K = 4 (every mode); double: 2 columns, K = 2
-    wanted = [("fdw_step_f32c2.hip", "IfLi4ELi2E"), ("fdw_step_f64c2.hip", "IdLi2ELi2E")]
+    # the defaults: float with 2 columns per lane, K = 8; double with 1 column, K = 8 (every mode)
+    wanted = [("fdw_step_f32c2.hip", "IfLi8ELi2E"), ("fdw_step_f64c1.hip", "IdLi8ELi1E")]
     for unit, tag in wanted:
         names = [n for n in _functions(asm[unit]) if "k_step" in n and tag in n and "persistent" not in n]
         assert names, (unit, tag)
