@@ -15,6 +15,7 @@ oracle timed on a bounded sample of the same workload.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
        python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: one 400-step
                         forward solve plus three plain copies used to calibrate the counters)
+       python bench.py --profile-run --adjoint   (short run of the reverse sweep for rocprofv3)
        python bench.py --summarize-profile DIR [DIR ...] --out NAME (writes profiles/NAME.txt,
                         and NAME.json with calibrated bytes per launch, from rocprofv3 CSV files)
 """
@@ -313,6 +314,29 @@ def profile_run(dtype_name: str):
     s.close()
 
 
+def profile_run_adjoint():
+    """Short, profiler-friendly run of the reverse sweep: the 2048^2 FP64 receiver-misfit
+    workload cut to 512 steps (checkpoints every 64), one forward solve recording traces and
+    checkpoints, then one adjoint from them."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+    from paper_2005_11931_amd import inputs as I
+
+    case, _ = I.adjoint_case(nsteps=512)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    rec = torch.as_tensor(case.receivers)
+    s.record_checkpoints(64)
+    tr = s.record_traces(rec)
+    s.step(case.nsteps)
+    J, tg = s.misfit(tr, torch.zeros_like(tr))
+    g = s.adjoint(rec, tg, ckpt_every=64)
+    torch.cuda.synchronize()
+    log("adjoint profile run done: K", s.config(fdw.FDW_CFG_ADJ_TIME_BLOCK), "C",
+        s.config(fdw.FDW_CFG_ADJ_LANE_COLUMNS), "|g|", float(g.abs().max()))
+    s.close()
+
+
 def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32"):
     """Collects kernel statistics and FETCH_SIZE / WRITE_SIZE counter rows from rocprofv3 CSV
     output under `dirs` into profiles/<name>.txt.  When both counters were taken for the
@@ -387,8 +411,12 @@ def main():
         ap = argparse.ArgumentParser()
         ap.add_argument("--profile-run", action="store_true")
         ap.add_argument("--dtype", default="f32")
+        ap.add_argument("--adjoint", action="store_true")
         a = ap.parse_args()
-        profile_run(a.dtype)
+        if a.adjoint:
+            profile_run_adjoint()
+        else:
+            profile_run(a.dtype)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -48,7 +48,9 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     constexpr int U = (K % 2 == 0) ? K : 2 * K;
     static_assert(U % NB == 0 && U % K == 0 && U % 2 == 0, "row unroll");
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + wave_in_block();
+    // XCD-contiguous block order, as in the forward kernel: neighbouring strips and segments
+    // (which read each other's halo rows and columns) then share an L2
+    const int wave = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_in_block();
     if (wave >= a.waves) return;
 
     const int nx = a.nx, ny = a.ny, ld = a.ld;
