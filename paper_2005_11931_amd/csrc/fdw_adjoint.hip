@@ -151,9 +151,12 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
         if (FACE) buffer_row<T, C>(rhy, off, hy);
     };
     // accumulator row of stream position p (the row completed NB - 1 iterations later)
+    // only the segment's own rows are accumulated, so only those are read (an out-of-range
+    // buffer offset costs no memory traffic)
     auto load_g = [&](int p, double (&g1)[C], double (&g2)[C]) {
         const int j = rfirst + dir * p;
-        const unsigned int goff = (j < jbase) ? kBufferOutOfRange : (unsigned int)(j - jbase) * grow_bytes + glane_col;
+        const unsigned int goff =
+            (j < r0 || j >= r1) ? kBufferOutOfRange : (unsigned int)(j - jbase) * grow_bytes + glane_col;
         buffer_row<double, C>(rg1, goff, g1);
         if (split) buffer_row<double, C>(rg2, goff, g2);
     };
