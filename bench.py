@@ -13,8 +13,8 @@ forward time ratio of the 2048^2 FP64 receiver-misfit gradient (4000 steps, chec
 oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--skip-cpu]
-       python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: one 400-step
-                        forward solve plus three plain copies used to calibrate the counters)
+       python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: three 800-step
+                        forward solves plus three plain copies used to calibrate the counters)
        python bench.py --profile-run --adjoint   (short run of the reverse sweep for rocprofv3)
        python bench.py --summarize-profile DIR [DIR ...] --out NAME (writes profiles/NAME.txt,
                         and NAME.json with calibrated bytes per launch, from rocprofv3 CSV files)
@@ -291,7 +291,7 @@ def cpu_baseline(I, budget_s=15.0):
 
 
 def profile_run(dtype_name: str):
-    """Short, profiler-friendly run: one 400-step forward solve of the 8192^2 workload with
+    """Short, profiler-friendly run: three 800-step forward solves of the 8192^2 workload with
     per-step energy (the configuration the bench times), then three state read-outs: each is a
     plain copy kernel (k_copy_out) that reads and writes exactly n*n words, used to calibrate
     the memory counters."""
@@ -304,7 +304,9 @@ def profile_run(dtype_name: str):
     case = I.point_case(n=8192, nsteps=5000)
     s = fdw.solver_for_case(case, dtype=dtype)
     del case
-    s.step(400, energy=True)
+    for _ in range(3):  # three 800-step solves: the average is over ~300 launches, warm-up included
+        s.reset()
+        s.step(800, energy=True)
     torch.cuda.synchronize()
     for _ in range(3):
         s.get_state()
@@ -337,7 +339,7 @@ def profile_run_adjoint():
     s.close()
 
 
-def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32"):
+def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32", factors=None):
     """Collects kernel statistics and FETCH_SIZE / WRITE_SIZE counter rows from rocprofv3 CSV
     output under `dirs` into profiles/<name>.txt.  When both counters were taken for the
     streaming kernel and for the calibration copy (k_copy_out: n*n words read and written per
@@ -364,7 +366,8 @@ def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32"):
                     val = float(r.get("Counter_Value", "nan"))
                 except ValueError:
                     continue
-                key = "copy" if "k_copy_out" in kname else ("k_step" if "k_step" in kname else None)
+                key = "copy" if "k_copy_out" in kname else ("k_step" if "k_step" in kname else
+                                                             ("k_adjoint" if "k_adjoint<" in kname else None))
                 if key is None:
                     continue
                 summary.setdefault((key, cname), []).append(val)
@@ -372,6 +375,16 @@ def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32"):
         lines.append("counters (KiB per dispatch, mean over dispatches):")
         for (k, c), v in sorted(summary.items()):
             lines.append(f"{k} {c} mean {sum(v) / len(v):.1f} over {len(v)} dispatches")
+    if factors and ("k_adjoint", "FETCH_SIZE") in summary and ("k_adjoint", "WRITE_SIZE") in summary:
+        # reverse sweep of the 2048^2 FP64 workload; counters scaled by the copy calibration
+        f_fetch, f_write = factors
+        rd = sum(summary[("k_adjoint", "FETCH_SIZE")]) / len(summary[("k_adjoint", "FETCH_SIZE")]) * f_fetch * 1024
+        wr = sum(summary[("k_adjoint", "WRITE_SIZE")]) / len(summary[("k_adjoint", "WRITE_SIZE")]) * f_write * 1024
+        n = 2048
+        lines += ["", f"reverse kernel (calibration factors fetch {f_fetch:.4f}, write {f_write:.4f} from the copy "
+                      f"of the forward profile run): {rd / 1e6:.1f} MB read + {wr / 1e6:.1f} MB written per launch "
+                      f"(algorithmic {6 * 8 * n * n / 1e6:.1f} MB read: u, du, lam, mu, h, g; "
+                      f"{5 * 8 * n * n / 1e6:.1f} MB written)"]
     need = [("copy", "FETCH_SIZE"), ("copy", "WRITE_SIZE"), ("k_step", "FETCH_SIZE"), ("k_step", "WRITE_SIZE")]
     if all(k in summary for k in need):
         mean = {k: sum(summary[k]) / len(summary[k]) for k in need}
@@ -404,8 +417,9 @@ def main():
         ap.add_argument("--out", required=True)
         ap.add_argument("--command", default="")
         ap.add_argument("--dtype", default="f32")
+        ap.add_argument("--factors", nargs=2, type=float, default=None)
         a = ap.parse_args()
-        summarize_profile(a.summarize_profile, a.out, a.command, a.dtype)
+        summarize_profile(a.summarize_profile, a.out, a.command, a.dtype, a.factors)
         return
     if "--profile-run" in sys.argv:
         ap = argparse.ArgumentParser()
