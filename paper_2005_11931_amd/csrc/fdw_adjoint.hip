@@ -262,6 +262,11 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                         GY[q][c] = __builtin_fma(-w * ayd, gy, GY[q][c]);
                     else
                         GX[q][c] = __builtin_fma(-w * ayd, gy, GX[q][c]);
+                    // pin the accumulation here: it is consumed only when the row completes,
+                    // and left alone the compiler may defer it there, keeping face products
+                    // of several rows alive
+                    asm volatile("" : "+v"(GX[q][c]));
+                    if (split) asm volatile("" : "+v"(GY[q][c]));
                     if (rin) {
                         nd[c] = fma_t(-Lu, colm[c], Dr[t - 1][pr][c]);
                         nm[c] = fma_t(Ll, colm[c], Mr[t - 1][pr][c]);
@@ -356,7 +361,8 @@ static hipError_t adj_launch_kc(const AdjArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int C>
+// reverse time blocks 1..KMAX of one (T, C) configuration
+template <typename T, int C, int KMAX>
 static hipError_t adj_launch_c(const AdjArgs& a, int K, int grid, hipStream_t s)
 {
     switch (K) {
@@ -364,22 +370,26 @@ static hipError_t adj_launch_c(const AdjArgs& a, int K, int grid, hipStream_t s)
     case 2: return adj_launch_kc<T, 2, C>(a, grid, s);
     case 3: return adj_launch_kc<T, 3, C>(a, grid, s);
     case 4: return adj_launch_kc<T, 4, C>(a, grid, s);
+    case 5: return KMAX >= 5 ? adj_launch_kc<T, (KMAX >= 5 ? 5 : 1), C>(a, grid, s) : hipErrorInvalidValue;
+    case 6: return KMAX >= 6 ? adj_launch_kc<T, (KMAX >= 6 ? 6 : 1), C>(a, grid, s) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
 
+// One 8-byte value per lane and row (FP32 pairs, FP64 singles) goes up to 6 reverse steps per
+// launch at two waves per SIMD; the wider configurations to 4.
 template <>
 hipError_t launch_adjoint_block<float>(const AdjArgs& a, int K, int C, int grid, hipStream_t s)
 {
-    if (C == 2) return adj_launch_c<float, 2>(a, K, grid, s);
-    if (C == 4) return adj_launch_c<float, 4>(a, K, grid, s);
+    if (C == 2) return adj_launch_c<float, 2, 6>(a, K, grid, s);
+    if (C == 4) return adj_launch_c<float, 4, 4>(a, K, grid, s);
     return hipErrorInvalidValue;
 }
 template <>
 hipError_t launch_adjoint_block<double>(const AdjArgs& a, int K, int C, int grid, hipStream_t s)
 {
-    if (C == 1) return adj_launch_c<double, 1>(a, K, grid, s);
-    if (C == 2) return adj_launch_c<double, 2>(a, K, grid, s);
+    if (C == 1) return adj_launch_c<double, 1, 6>(a, K, grid, s);
+    if (C == 2) return adj_launch_c<double, 2, 4>(a, K, grid, s);
     return hipErrorInvalidValue;
 }
 

@@ -180,6 +180,9 @@ void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int
     md.blocks = (md.waves + kWavesPerBlock - 1) / kWavesPerBlock;
 }
 
+// reverse-sweep configurations with one 8-byte value per lane and row (time blocks up to 6)
+bool adj_narrow(int dtype, int C) { return (dtype == FDW_F64) ? C == 1 : C == 2; }
+
 int choose_K(const fdw_ctx* c)
 {
     if (c->K_cfg > 0) return c->K_cfg;
@@ -663,7 +666,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
     c->dtype = problems[0].dtype;
     c->C = default_cols_per_lane(c->dtype);
     c->adjC = (c->dtype == FDW_F64) ? 1 : 2;
-    c->adjK = 4;
+    c->adjK = (c->dtype == FDW_F64) ? 6 : 4;  // the deepest reverse blocks at two waves per SIMD
     c->stream = (hipStream_t)hip_stream;
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
@@ -1018,14 +1021,18 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         c->C = (int)v;
         break;
     case FDW_CFG_ADJ_TIME_BLOCK:
-        if (v == 0) v = 4;
-        if (v < 1 || v > 4) return fail(c, FDW_EINVAL, "adjoint time block must be 1..4");
+        if (v == 0) v = (c->dtype == FDW_F64 && c->adjC == 1) ? 6 : 4;
+        if (v < 1 || v > 6 || (v > 4 && !adj_narrow(c->dtype, c->adjC)))
+            return fail(c, FDW_EINVAL, "adjoint time block must be 1..6 (double with 1 column per lane, float with 2) "
+                                       "or 1..4");
         c->adjK = (int)v;
         break;
     case FDW_CFG_ADJ_LANE_COLUMNS:
         if (v == 0) v = (c->dtype == FDW_F64) ? 1 : 2;
         if (!(v == 2 || (v == 4 && c->dtype == FDW_F32) || (v == 1 && c->dtype == FDW_F64)))
             return fail(c, FDW_EINVAL, "adjoint lane columns must be 2 or 4 (float) / 1 or 2 (double)");
+        if (c->adjK > 4 && !adj_narrow(c->dtype, (int)v))
+            return fail(c, FDW_EINVAL, "adjoint time blocks above 4 need 1 (double) or 2 (float) columns per lane");
         c->adjC = (int)v;
         break;
     case FDW_CFG_ADJ_SEGMENT_ROWS:
@@ -1082,17 +1089,14 @@ namespace {
 
 int adjoint_K(const fdw_ctx* c) { return c->adjK; }
 
-// Rows per reverse work item: the reverse kernel holds about twice the registers of the
-// forward one (two waves per SIMD); aim at 8192 waves, with segments of at least 16 rows.
+// Rows per reverse work item: 4K, at least 16 (measured best at 2048^2: 16 rows at K = 4,
+// 24 at K = 6); short items keep many waves in flight for this register-heavy kernel, and the
+// 2K halo rows of an item are largely shared with its neighbours through L2.
 int choose_adj_S(const fdw_ctx* c, const HostMember& hm)
 {
     if (c->adjS_cfg > 0) return c->adjS_cfg;
-    const int Hx = ((c->adjK + c->adjC - 1) / c->adjC) * c->adjC;
-    const int Wv = kWaveSize * c->adjC - 2 * Hx;
-    const int64_t strips = (hm.nx + Wv - 1) / Wv;
-    int64_t S = (hm.ny * strips + 8191) / 8192;
-    S = std::max<int64_t>(kMinSegRows, (S + 7) / 8 * 8);
-    return (int)std::min<int64_t>(S, std::max<int64_t>(kMinSegRows, align_up((size_t)hm.ny, 8)));
+    const int S = std::max(kMinSegRows, (4 * c->adjK + 7) / 8 * 8);
+    return std::min(S, std::max(kMinSegRows, (int)align_up((size_t)hm.ny, 8)));
 }
 
 void adj_decompose(const fdw_ctx* c, const HostMember& hm, int K, int S, AdjArgs& a)
