@@ -10,15 +10,16 @@
 namespace fdw {
 
 // ------------------------------------------------------------------------------------------
-// Lane exchange across the whole wave (DPP wave shift by one lane; lanes with no source get 0)
+// Lane exchange across the whole wave (DPP wave shift by one lane; lanes with no source get 0
+// through the bound control bit, so no register has to be cleared first)
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ int lane_from_left_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // lane l <- lane l-1
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);  // lane l <- lane l-1
 }
 __device__ __forceinline__ int lane_from_right_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // lane l <- lane l+1
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);  // lane l <- lane l+1
 }
 __device__ __forceinline__ float lane_from_left(float v)
 {
