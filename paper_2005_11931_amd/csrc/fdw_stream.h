@@ -163,6 +163,12 @@ struct RowUnroll {
 };
 __host__ __device__ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
+// compile-time flag passed to generic lambdas (selects a specialised copy of a loop body)
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+
 // Row loads go through buffer resources: an offset at or beyond the resource's size returns
 // zeros in hardware, so rows above/below the grid and lanes outside the plane need no branch
 // (a load under a divergent branch would force the prefetch to be waited on at once).
@@ -326,148 +332,154 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
 #pragma unroll
     for (int q = 0; q < NB - 1; ++q) load_row(q, bu[q], bd[q], bh[q], bhy[q]);
 
-    for (int blk = 0; blk < nblk; ++blk) {
-        T eb[K];
+    {
+        for (int blk = 0; blk < nblk; ++blk) {
+            T eb[K];
 #pragma unroll
-        for (int t = 0; t < K; ++t) eb[t] = T(0);
+            for (int t = 0; t < K; ++t) eb[t] = T(0);
 #pragma unroll
-        for (int s = 0; s < U; ++s) {
-            const int p = blk * U + s;  // stream position of the row loaded last
-            const int pb = s % NB;      // buffer holding row p
-            // prefetch row p+NB-1 into the buffer row p-1 used
-            {
-                const int pn = (s + NB - 1) % NB;
-                load_row(p + NB - 1, bu[pn], bd[pn], bh[pn], bhy[pn]);
-            }
+            for (int s = 0; s < U; ++s) {
+                const int p = blk * U + s;  // stream position of the row loaded last
+                const int pb = s % NB;      // buffer holding row p
+                // prefetch row p+NB-1 into the buffer row p-1 used
+                {
+                    const int pn = (s + NB - 1) % NB;
+                    load_row(p + NB - 1, bu[pn], bd[pn], bh[pn], bhy[pn]);
+                }
 
-            // ---- coefficient faces of row p-1 into the ring (index (p-1) mod K); the y face
-            // between rows p-1 and p is stored with the upper of the two grid rows
-            {
-                const int q = pmod(s - 1, K);
-                if (FACE) {
+                // ---- coefficient faces of row p-1 into the ring (index (p-1) mod K), scaled
+                // by tau^2/(2 dx^2) and tau^2/(2 dy^2) once per row, so that every level's
+                // operator is the plain sum of its x and y flux differences; the y face between
+                // rows p-1 and p is stored with the upper of the two grid rows
+                {
+                    const int q = pmod(s - 1, K);
+                    if (FACE) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            FXr[q][c] = ax * hprev[c];
+                            FYr[q][c] = ay * ((dir > 0) ? hyprev[c] : bhy[pb][c]);
+                            hprev[c] = bh[pb][c];
+                            hyprev[c] = bhy[pb][c];
+                        }
+                    } else {
+                        const T hr = lane_from_right(hprev[0]);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            FXr[q][c] = ax * (hprev[c] + ((c < C - 1) ? hprev[c + 1] : hr));
+                            FYr[q][c] = ay * (hprev[c] + bh[pb][c]);
+                        }
+#pragma unroll
+                        for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
+                    }
+                }
+                // ---- level 0: row p of the input state
+                {
+                    const int p0 = pmod(s, 2);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        FXr[q][c] = hprev[c];
-                        FYr[q][c] = (dir > 0) ? hyprev[c] : bhy[pb][c];
-                        hprev[c] = bh[pb][c];
-                        hyprev[c] = bhy[pb][c];
+                        Ur[0][p0][c] = bu[pb][c];
+                        Dr[0][p0][c] = bd[pb][c];
                     }
-                } else {
-                    const T hr = lane_from_right(hprev[0]);
+                }
+                // ---- levels 1..K
+#pragma unroll
+                for (int t = 1; t <= K; ++t) {
+                    const int r = rfirst + dir * (p - t);  // grid row of stream position p - t
+                    const int pr = pmod(s - t, 2);         // parity index of row r
+                    const int pr1 = pmod(s - t + 1, 2);    // ... of the next row in the stream, r + dir
+                    const int q = pmod(s - t, K);          // coefficient ring index of row r
+                    const bool rin = (r >= 1) && (r <= ny - 2);
+                    const bool rown = (r >= r0) && (r < r1);
+                    const T right = lane_from_right(Ur[t - 1][pr][0]);
+                    T F[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        FXr[q][c] = hprev[c] + ((c < C - 1) ? hprev[c + 1] : hr);
-                        FYr[q][c] = hprev[c] + bh[pb][c];
+                        const T ue = (c < C - 1) ? Ur[t - 1][pr][c + 1] : right;
+                        F[c] = FXr[q][c] * (ue - Ur[t - 1][pr][c]);
                     }
-#pragma unroll
-                    for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
-                }
-            }
-            // ---- level 0: row p of the input state
-            {
-                const int p0 = pmod(s, 2);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    Ur[0][p0][c] = bu[pb][c];
-                    Dr[0][p0][c] = bd[pb][c];
-                }
-            }
-            // ---- levels 1..K
-#pragma unroll
-            for (int t = 1; t <= K; ++t) {
-                const int r = rfirst + dir * (p - t);  // grid row of stream position p - t
-                const int pr = pmod(s - t, 2);      // parity index of row r
-                const int pr1 = pmod(s - t + 1, 2); // ... of the next row in the stream, r + dir
-                const int q = pmod(s - t, K);       // coefficient ring index of row r
-                const bool rin = (r >= 1) && (r <= ny - 2);
-                const bool rown = (r >= r0) && (r < r1);
-                const T right = lane_from_right(Ur[t - 1][pr][0]);
-                T F[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const T ue = (c < C - 1) ? Ur[t - 1][pr][c + 1] : right;
-                    F[c] = FXr[q][c] * (ue - Ur[t - 1][pr][c]);
-                }
-                const T Fl = lane_from_left(F[C - 1]);
-                T nu[C], nd[C], L[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    // Gn = fy (u_{r+dir} - u_r): downwards this is F_{r+1/2}, upwards it is
-                    // -F_{r-1/2} exactly (negation is exact), and Gy holds the previous row's
-                    // Gn; so Gn - Gy is F_{r+1/2} - F_{r-1/2} bit for bit in both directions
-                    const T Gn = FYr[q][c] * (Ur[t - 1][pr1][c] - Ur[t - 1][pr][c]);
-                    const T sx = F[c] - ((c > 0) ? F[c - 1] : Fl);
-                    const T sy = Gn - Gy[t - 1][c];
-                    Gy[t - 1][c] = Gn;
-                    L[c] = fma_t(ax, sx, ay * sy);
-                }
-                if (rin) {
+                    const T Fl = lane_from_left(F[C - 1]);
+                    T nu[C], nd[C], L[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        nd[c] = fma_t(L[c], colm[c], Dr[t - 1][pr][c]);
-                        nu[c] = Ur[t - 1][pr][c] + nd[c];
+                        // Gn = fy (u_{r+dir} - u_r): downwards this is F_{r+1/2}, upwards it is
+                        // -F_{r-1/2} exactly (negation is exact), and Gy holds the previous
+                        // row's Gn; so Gn - Gy is F_{r+1/2} - F_{r-1/2} bit for bit in both
+                        // directions
+                        const T Gn = FYr[q][c] * (Ur[t - 1][pr1][c] - Ur[t - 1][pr][c]);
+                        const T sx = F[c] - ((c > 0) ? F[c - 1] : Fl);
+                        const T sy = Gn - Gy[t - 1][c];
+                        Gy[t - 1][c] = Gn;
+                        L[c] = sx + sy;
                     }
-                } else {
+                    // Dirichlet rows keep du = 0 (and with it u = 0, which they hold at every
+                    // level); the row test is wave-uniform, and the empty asm keeps it a scalar
+                    // branch instead of a select per value
 #pragma unroll
-                    for (int c = 0; c < C; ++c) nd[c] = nu[c] = T(0);
-                }
-                if (want_energy && rown) {
-                    // per-node terms du^2 - u L in the storage type, summed over the lane's
-                    // columns and the rows of this unrolled block; FP64 across blocks
-                    T ps = T(0);
+                    for (int c = 0; c < C; ++c) nd[c] = fma_t(L[c], colm[c], Dr[t - 1][pr][c]);
+                    if (!rin) {
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        ps = fma_t(nd[c], nd[c], ps);
-                        ps = fma_t(-nu[c], L[c], ps);
+                        for (int c = 0; c < C; ++c) nd[c] = T(0);
+                        asm volatile("");
                     }
-                    eb[t - 1] += ps;
-                    // an empty asm that reads and writes the partial sum pins this addition
-                    // here: otherwise the compiler defers the energy arithmetic of the whole
-                    // unrolled block to its end, keeping every level's nu, nd and L of every
-                    // row alive (several hundred registers at K >= 3)
-                    asm volatile("" : "+v"(eb[t - 1]));
-                }
-                if (want_trace && rown && rin) {
-                    const ConstPtr<int> rowptr = (ConstPtr<int>)M.rec_rowptr;
-                    const ConstPtr<int> rcol = (ConstPtr<int>)M.rec_col;
-                    const ConstPtr<int> rid = (ConstPtr<int>)M.rec_id;
-                    const int kb = rowptr[r], ke = rowptr[r + 1];
-                    const int64_t row = n0 + t;
-                    if (kb < ke && row < M.trace_rows) {
-                        for (int k = kb; k < ke; ++k) {
-                            const int off = rcol[k] - cb;
-                            if (lane_owned && off >= 0 && off < C) {
-                                T v = nu[0];
 #pragma unroll
-                                for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
-                                ((T*)M.traces)[row * M.R + rid[k]] = v;
+                    for (int c = 0; c < C; ++c) nu[c] = Ur[t - 1][pr][c] + nd[c];
+                    if (want_energy && rown) {
+                        // per-node terms du^2 - u L in the storage type, summed over the lane's
+                        // columns and the rows of this unrolled block; FP64 across blocks
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            eb[t - 1] = fma_t(nd[c], nd[c], eb[t - 1]);
+                            eb[t - 1] = fma_t(-nu[c], L[c], eb[t - 1]);
+                        }
+                        // an empty asm that reads and writes the partial sum pins the
+                        // accumulation here: otherwise the compiler defers the energy
+                        // arithmetic of the whole unrolled block to its end, keeping every
+                        // level's nu, nd and L of every row alive (several hundred registers
+                        // at K >= 3)
+                        asm volatile("" : "+v"(eb[t - 1]));
+                    }
+                    if (want_trace && rown && rin) {
+                        const ConstPtr<int> rowptr = (ConstPtr<int>)M.rec_rowptr;
+                        const ConstPtr<int> rcol = (ConstPtr<int>)M.rec_col;
+                        const ConstPtr<int> rid = (ConstPtr<int>)M.rec_id;
+                        const int kb = rowptr[r], ke = rowptr[r + 1];
+                        const int64_t row = n0 + t;
+                        if (kb < ke && row < M.trace_rows) {
+                            for (int k = kb; k < ke; ++k) {
+                                const int off = rcol[k] - cb;
+                                if (lane_owned && off >= 0 && off < C) {
+                                    T v = nu[0];
+#pragma unroll
+                                    for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
+                                    ((T*)M.traces)[row * M.R + rid[k]] = v;
+                                }
                             }
                         }
                     }
-                }
-                if (t < K) {
+                    if (t < K) {
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        Ur[t][pr][c] = nu[c];
-                        Dr[t][pr][c] = nd[c];
-                    }
-                } else if (rown && lane_owned) {
-                    const size_t off = (size_t)(ptrdiff_t)r * ld + lane_off;
-                    if (nt) {
-                        store_row_nt<T, C>(uout + off, nu);
-                        store_row_nt<T, C>(dout + off, nd);
-                    } else {
-                        store_pack<T, C>(uout + off, nu);
-                        store_pack<T, C>(dout + off, nd);
+                        for (int c = 0; c < C; ++c) {
+                            Ur[t][pr][c] = nu[c];
+                            Dr[t][pr][c] = nd[c];
+                        }
+                    } else if (rown && lane_owned) {
+                        const size_t off = (size_t)(ptrdiff_t)r * ld + lane_off;
+                        if (nt) {
+                            store_row_nt<T, C>(uout + off, nu);
+                            store_row_nt<T, C>(dout + off, nd);
+                        } else {
+                            store_pack<T, C>(uout + off, nu);
+                            store_pack<T, C>(dout + off, nd);
+                        }
                     }
                 }
+                // keep the scheduler from interleaving consecutive rows (bounds register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
-            // keep the scheduler from interleaving consecutive rows (bounds register pressure)
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (want_energy && lane_owned) {
+            if (want_energy && lane_owned) {
 #pragma unroll
-            for (int t = 0; t < K; ++t) acc[t] += (double)eb[t];
+                for (int t = 0; t < K; ++t) acc[t] += (double)eb[t];
+            }
         }
     }
 
