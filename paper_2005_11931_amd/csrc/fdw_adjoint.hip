@@ -177,15 +177,16 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                 load_row(p + NB - 1, bu[pn], bd[pn], bl[pn], bm[pn], bh[pn], bhy[pn]);
                 load_g(p + NB - 1 - K, gbuf[pn], g2buf[pn]);
             }
-            // coefficient faces of row p-1 (the y face between rows p-1 and p is stored with
-            // the upper of the two grid rows)
+            // coefficient faces of row p-1, scaled by tau^2/(2 dx^2) and tau^2/(2 dy^2) as in
+            // the forward kernel (the y face between rows p-1 and p is stored with the upper of
+            // the two grid rows)
             {
                 const int q = pmod(s - 1, K);
                 if (FACE) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        FXr[q][c] = hprev[c];
-                        FYr[q][c] = (dir > 0) ? hyprev[c] : bhy[pb][c];
+                        FXr[q][c] = ax * hprev[c];
+                        FYr[q][c] = ay * ((dir > 0) ? hyprev[c] : bhy[pb][c]);
                         hprev[c] = bh[pb][c];
                         hyprev[c] = bhy[pb][c];
                     }
@@ -193,8 +194,8 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     const T hr = lane_from_right(hprev[0]);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        FXr[q][c] = hprev[c] + ((c < C - 1) ? hprev[c + 1] : hr);
-                        FYr[q][c] = hprev[c] + bh[pb][c];
+                        FXr[q][c] = ax * (hprev[c] + ((c < C - 1) ? hprev[c + 1] : hr));
+                        FYr[q][c] = ay * (hprev[c] + bh[pb][c]);
                     }
 #pragma unroll
                     for (int c = 0; c < C; ++c) hprev[c] = bh[pb][c];
@@ -218,14 +219,14 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                 const int pr1 = pmod(s - t + 1, 2);
                 const int q = pmod(s - t, K);
                 const bool rin = (r >= 1) && (r <= ny - 2);
-                const bool r1in = (r + dir >= 1) && (r + dir <= ny - 2);  // the next row in the stream
                 const bool rown = (r >= r0) && (r < r1);
                 const int64_t n = a.n_top - t;  // time of this level's forward state
                 const double w = (n == 0) ? 0.5 : 1.0;
-                // u^{m-t}(r+1) = u^{m-t+1}(r+1) - du^{m-t+1}(r+1)
+                // u^{m-t}(r+1) = u^{m-t+1}(r+1) - du^{m-t+1}(r+1); u and du are zero on the
+                // Dirichlet rows at every level (and rows outside the grid load as zero), so
+                // this needs no row test
 #pragma unroll
-                for (int c = 0; c < C; ++c)
-                    Ur[t][pr1][c] = r1in ? fma_t(-Dr[t - 1][pr1][c], colm[c], Ur[t - 1][pr1][c]) : T(0);
+                for (int c = 0; c < C; ++c) Ur[t][pr1][c] = fma_t(-Dr[t - 1][pr1][c], colm[c], Ur[t - 1][pr1][c]);
                 // x fluxes and face differences of u^{m-t} and lam^{m-t+1} at row r
                 const T uR = lane_from_right(Ur[t][pr][0]);
                 const T lR = lane_from_right(Lr[t - 1][pr][0]);
@@ -250,8 +251,8 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     const T Gun = FYr[q][c] * duy;
                     const T Gln = FYr[q][c] * dly;
                     const double Pyn = (double)duy * (double)dly;
-                    const T Lu = fma_t(ax, Fu[c] - ((c > 0) ? Fu[c - 1] : FuL), ay * (Gun - Gu[t - 1][c]));
-                    const T Ll = fma_t(ax, Fl[c] - ((c > 0) ? Fl[c - 1] : FlL), ay * (Gln - Gl[t - 1][c]));
+                    const T Lu = (Fu[c] - ((c > 0) ? Fu[c - 1] : FuL)) + (Gun - Gu[t - 1][c]);
+                    const T Ll = (Fl[c] - ((c > 0) ? Fl[c - 1] : FlL)) + (Gln - Gl[t - 1][c]);
                     Gu[t - 1][c] = Gun;
                     Gl[t - 1][c] = Gln;
                     const double gx = Px[c] + ((c > 0) ? Px[c - 1] : PxL);
@@ -267,12 +268,15 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     // of several rows alive
                     asm volatile("" : "+v"(GX[q][c]));
                     if (split) asm volatile("" : "+v"(GY[q][c]));
-                    if (rin) {
-                        nd[c] = fma_t(-Lu, colm[c], Dr[t - 1][pr][c]);
-                        nm[c] = fma_t(Ll, colm[c], Mr[t - 1][pr][c]);
-                    } else {
-                        nd[c] = nm[c] = T(0);
-                    }
+                    nd[c] = fma_t(-Lu, colm[c], Dr[t - 1][pr][c]);
+                    nm[c] = fma_t(Ll, colm[c], Mr[t - 1][pr][c]);
+                }
+                // Dirichlet rows keep du = mu = 0 (and with them u = lam = 0); the row test is
+                // wave-uniform, and the empty asm keeps it a scalar branch instead of selects
+                if (!rin) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) nd[c] = nm[c] = T(0);
+                    asm volatile("");
                 }
                 if (t == 1 && any_rec) {
                     RPb[q] = rin ? rowptr[r] : 0;
@@ -291,7 +295,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < C; ++c) nl[c] = rin ? fma_t(nm[c], colm[c], Lr[t - 1][pr][c]) : T(0);
+                for (int c = 0; c < C; ++c) nl[c] = fma_t(nm[c], colm[c], Lr[t - 1][pr][c]);
                 if (t < K) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
