@@ -41,10 +41,10 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
 {
     constexpr int Hx = ((K + C - 1) / C) * C;
     constexpr int Wv = kWaveSize * C - 2 * Hx;
-    // rows are loaded one row ahead: this kernel holds twice the forward's registers, and a
-    // deeper prefetch buys nothing measurable at two waves per SIMD while pushing the FP32
-    // variants to one wave
-    constexpr int NB = 2;
+    // rows are loaded NB - 1 rows ahead: two rows for FP64 with one column per lane and K a
+    // multiple of 3 (the default reverse configuration, which stays at two waves per SIMD),
+    // one row elsewhere (a deeper prefetch would push the FP32 variants to one wave)
+    constexpr int NB = (sizeof(T) == 8 && C == 1 && K % 3 == 0) ? 3 : 2;
     constexpr int U = (K % 2 == 0) ? K : 2 * K;
     static_assert(U % NB == 0 && U % K == 0 && U % 2 == 0, "row unroll");
     const int lane = threadIdx.x & 63;
