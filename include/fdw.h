@@ -193,7 +193,8 @@ enum {
     FDW_CFG_ADJ_LANE_COLUMNS = 8, /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
                                      0 = default (2 for float, 1 for double) */
     FDW_CFG_ADJ_SEGMENT_ROWS = 9  /* rows per work item of the adjoint sweep, 16..4096 (0 = automatic: 4 x the
-                                     reverse time block, at least 16) */
+                                     reverse time block, at least 16; lengthened, up to 16 x the block,
+                                     until one launch's items fit in the waves the device holds at once) */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);

@@ -397,6 +397,58 @@ hipError_t launch_adjoint_block<double>(const AdjArgs& a, int K, int C, int grid
     return hipErrorInvalidValue;
 }
 
+// Work items (waves) of one reverse launch that the device holds at once, for the item-size
+// choice: a launch whose items exceed this by a little runs a second, mostly idle round.
+template <typename T, int K, int C>
+static int adj_resident_kc(bool face, bool split)
+{
+    int per_cu = 0;
+    const int bs = kWaveSize * kWavesPerBlock;
+    hipError_t e;
+    if (face && split)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<T, K, C, 1, 1>, bs, 0);
+    else if (face)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<T, K, C, 1, 0>, bs, 0);
+    else if (split)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<T, K, C, 0, 1>, bs, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adjoint<T, K, C, 0, 0>, bs, 0);
+    if (e != hipSuccess) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus * kWavesPerBlock;
+}
+
+template <typename T, int C, int KMAX>
+static int adj_resident_c(int K, bool face, bool split)
+{
+    switch (K) {
+    case 1: return adj_resident_kc<T, 1, C>(face, split);
+    case 2: return adj_resident_kc<T, 2, C>(face, split);
+    case 3: return adj_resident_kc<T, 3, C>(face, split);
+    case 4: return adj_resident_kc<T, 4, C>(face, split);
+    case 5: return KMAX >= 5 ? adj_resident_kc<T, (KMAX >= 5 ? 5 : 1), C>(face, split) : 0;
+    case 6: return KMAX >= 6 ? adj_resident_kc<T, (KMAX >= 6 ? 6 : 1), C>(face, split) : 0;
+    default: return 0;
+    }
+}
+
+template <>
+int adjoint_resident_waves<float>(int K, int C, bool face, bool split)
+{
+    if (C == 2) return adj_resident_c<float, 2, 6>(K, face, split);
+    if (C == 4) return adj_resident_c<float, 4, 4>(K, face, split);
+    return 0;
+}
+template <>
+int adjoint_resident_waves<double>(int K, int C, bool face, bool split)
+{
+    if (C == 1) return adj_resident_c<double, 1, 6>(K, face, split);
+    if (C == 2) return adj_resident_c<double, 2, 4>(K, face, split);
+    return 0;
+}
+
 // lam^N = mu^N = s_N at the receivers (planes already zero).
 template <typename T>
 __global__ void k_adjoint_seed(T* lam, T* mu, int ld, const int* rec_ij, int R, const double* tg)

@@ -1092,13 +1092,6 @@ int adjoint_K(const fdw_ctx* c) { return c->adjK; }
 // Rows per reverse work item: 4K, at least 16 (measured best at 2048^2: 16 rows at K = 4,
 // 24 at K = 6); short items keep many waves in flight for this register-heavy kernel, and the
 // 2K halo rows of an item are largely shared with its neighbours through L2.
-int choose_adj_S(const fdw_ctx* c, const HostMember& hm)
-{
-    if (c->adjS_cfg > 0) return c->adjS_cfg;
-    const int S = std::max(kMinSegRows, (4 * c->adjK + 7) / 8 * 8);
-    return std::min(S, std::max(kMinSegRows, (int)align_up((size_t)hm.ny, 8)));
-}
-
 void adj_decompose(const fdw_ctx* c, const HostMember& hm, int K, int S, AdjArgs& a)
 {
     const int C = c->adjC;
@@ -1108,6 +1101,28 @@ void adj_decompose(const fdw_ctx* c, const HostMember& hm, int K, int S, AdjArgs
     a.segs = (hm.ny + S - 1) / S;
     a.strips = (hm.nx + Wv - 1) / Wv;
     a.waves = a.strips * a.segs;
+}
+
+// Rows per reverse work item.  The default is 4K (at least 16): every item recomputes 2K halo
+// rows, so shorter items waste more, longer ones leave fewer items to fill the device.  When
+// the 4K-row items of a small grid need a second round of resident waves (the reverse kernel
+// holds two per SIMD), that round is mostly idle and costs a whole item time; the items are
+// then lengthened, in steps of 8 rows up to 16K, until they fit in one round.
+template <typename T>
+int choose_adj_S(const fdw_ctx* c, const HostMember& hm, int K, bool split)
+{
+    if (c->adjS_cfg > 0) return c->adjS_cfg;
+    const int cap = std::max(kMinSegRows, (int)align_up((size_t)hm.ny, 8));
+    const int S0 = std::min(std::max(kMinSegRows, (4 * K + 7) / 8 * 8), cap);
+    const int resident = adjoint_resident_waves<T>(K, c->adjC, hm.face != 0, split);
+    AdjArgs a;
+    adj_decompose(c, hm, K, S0, a);
+    if (resident <= 0 || a.waves <= resident) return S0;
+    for (int S = S0 + 8; S <= std::min(16 * K, cap); S += 8) {
+        adj_decompose(c, hm, K, S, a);
+        if (a.waves <= resident) return S;
+    }
+    return S0;
 }
 
 template <typename T>
@@ -1247,7 +1262,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
     int fcur = recorded ? 1 : cur;  // the first reverse output goes to the other state plane
     int lcur = 0;
     const int Kr = adjoint_K(c);
-    const int Sr = choose_adj_S(c, hm);
+    const int Sr = choose_adj_S<T>(c, hm, Kr, g2_out != nullptr);
     int64_t mtop = N;
     while (mtop > 0) {
         if (mtop < N && mtop % ck == 0) {

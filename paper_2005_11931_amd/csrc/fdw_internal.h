@@ -137,6 +137,9 @@ struct AdjArgs {
 };
 template <typename T>
 hipError_t launch_adjoint_block(const AdjArgs& a, int K, int C, int grid, hipStream_t s);
+// waves of the reverse kernel (K, C, layout) the device holds at once (0 if unknown)
+template <typename T>
+int adjoint_resident_waves(int K, int C, bool face, bool split);
 template <typename T>
 hipError_t launch_adjoint_seed(const AdjArgs& a, int64_t N, hipStream_t s);
 hipError_t launch_grad_out(const double* g, int ld, int nx, int ny, double* out, hipStream_t s);
