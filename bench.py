@@ -256,7 +256,10 @@ def adjoint_bench(fdw, torch, I, steps, warmup):
 
     tf = timed(fwd)
     ta = timed(adj)
+    # the forward run of a gradient evaluation records the receiver traces as well
+    s.record_traces(rec)
     tfr = timed(fwd_rec)
+    s.record_traces(None)
     tar = timed(adj_rec)
     s.close()
     return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, forward_recording_s=tfr, adjoint_recorded_s=tar,
@@ -538,8 +541,9 @@ def main():
                           "workload": "2048x2048 FP64 receiver-misfit gradient, 4000 steps, 64 receivers, "
                                       "checkpoints every 64 steps; ratio: adjoint call with its own forward replay "
                                       "/ forward solve; ratio_recorded: adjoint call from checkpoints stored by the "
-                                      "forward solve / forward solve; gradient_ratio: (forward solve storing "
-                                      "checkpoints + adjoint from them) / forward solve"}
+                                      "forward solve / forward solve; gradient_ratio: (forward solve recording the "
+                                      "receiver traces and storing checkpoints + adjoint from them) / forward "
+                                      "solve"}
     if not args.skip_extra:
         torch.cuda.empty_cache()
         log("small 256^2 fp64 line")

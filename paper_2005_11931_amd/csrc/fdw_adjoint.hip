@@ -100,6 +100,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     const ConstPtr<int> rid = (ConstPtr<int>)a.rec_id;
     const ConstPtr<double> tgrad = (ConstPtr<double>)a.trace_grad;
     const bool any_rec = a.R > 0;
+    const int col_lo = strip * Wv - Hx;  // first column the strip computes
     T* __restrict__ uout = (T*)a.uout;
     T* __restrict__ dout = (T*)a.dout;
     T* __restrict__ lout = (T*)a.lout;
@@ -279,8 +280,19 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     asm volatile("");
                 }
                 if (t == 1 && any_rec) {
-                    RPb[q] = rin ? rowptr[r] : 0;
-                    RPe[q] = rin ? rowptr[r + 1] : 0;
+                    // receivers of row r in the columns this strip computes (halo included:
+                    // every copy of a node takes its source), once per row
+                    int kb = 0, ke = 0;
+                    if (rin) {
+                        kb = rowptr[r];
+                        ke = rowptr[r + 1];
+                        if (kb < ke) {
+                            kb = lower_bound_col(rcol, kb, ke, col_lo);
+                            ke = lower_bound_col(rcol, kb, ke, col_lo + kWaveSize * C);
+                        }
+                    }
+                    RPb[q] = kb;
+                    RPe[q] = ke;
                 }
                 if (any_rec && rin) {
                     const int kb = RPb[q], ke = RPe[q];

@@ -60,6 +60,7 @@ struct HostMember {
     double* epart = nullptr;
     int epart_stride = 0;
     int R = 0;
+    int ndup = 0;  // receivers sharing a node with an earlier one (their traces are copied)
     void* traces = nullptr;
     size_t plane_bytes = 0;
 };
@@ -828,7 +829,18 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
 {
     if (!c) return FDW_EINVAL;
     if (n < 0) return fail(c, FDW_EINVAL, "n must be >= 0");
-    return (c->dtype == FDW_F32) ? step_n_impl<float>(c, n, energy_dev) : step_n_impl<double>(c, n, energy_dev);
+    std::vector<int64_t> n_before;
+    for (const HostMember& hm : c->m) n_before.push_back(hm.n);
+    const int rc = (c->dtype == FDW_F32) ? step_n_impl<float>(c, n, energy_dev) : step_n_impl<double>(c, n, energy_dev);
+    if (rc) return rc;
+    // coincident receivers: the kernels recorded the first of each run; copy the others
+    for (size_t i = 0; i < c->m.size(); ++i) {
+        const HostMember& hm = c->m[i];
+        if (hm.R <= 0 || !hm.traces || hm.ndup <= 0) continue;
+        const int64_t lo = n_before[i] + 1, hi = std::min<int64_t>(hm.n, hm.N);
+        HIPCHK(c, launch_trace_dups(hm.traces, (int)elem_size(c->dtype), hm.R, hm.rec_ij, hm.rid, lo, hi, c->stream));
+    }
+    return FDW_OK;
 }
 
 int fdw_energy(fdw_ctx* c, double* energy_host)
@@ -858,6 +870,7 @@ int fdw_record_traces(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, 
     if (R < 0 || R > kMaxReceivers) return fail(c, FDW_EINVAL, "R out of range");
     if (R == 0 || !traces) {
         hm.R = 0;
+        hm.ndup = 0;
         hm.traces = nullptr;
         sync_member_dev(c, m);
         invalidate_graphs(c);
@@ -866,17 +879,19 @@ int fdw_record_traces(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, 
     if (!recv_ij) return fail(c, FDW_EINVAL, "recv_ij is NULL");
     HIPCHK(c, hipMemcpyAsync(hm.rec_ij, recv_ij, sizeof(int) * 2 * (size_t)R, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, launch_receivers_csr(hm.rec_ij, R, hm.nx, hm.ny, hm.rowptr, hm.rcol, hm.rid, c->status, c->stream));
-    int st = -1;
-    HIPCHK(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    int st[2] = {-1, 0};
+    HIPCHK(c, hipMemcpyAsync(st, c->status, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (st != 0) {
+    if (st[0] != 0) {
         hm.R = 0;
+        hm.ndup = 0;
         hm.traces = nullptr;
         sync_member_dev(c, m);
         push_member(c, m);
         return fail(c, FDW_EINVAL, "receivers must be interior nodes (1 <= i <= nx-2, 1 <= j <= ny-2)");
     }
     hm.R = R;
+    hm.ndup = st[1];
     hm.traces = traces;
     sync_member_dev(c, m);
     invalidate_graphs(c);

@@ -106,6 +106,9 @@ hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s);
 template <typename T>
 hipError_t launch_diff_norm(const void* a, const void* b, int ld, int nx, int ny, double scale, double* red,
                             double* out, hipStream_t s);
+// copies the trace columns of coincident receivers (rows lo..hi of a [rows][R] trace array)
+hipError_t launch_trace_dups(void* traces, int es, int R, const int* rec_ij, const int* id, int64_t lo, int64_t hi,
+                             hipStream_t s);
 hipError_t launch_receivers_csr(const int* rec_ij, int R, int nx, int ny, int* rowptr, int* col, int* id,
                                 int* status, hipStream_t s);
 

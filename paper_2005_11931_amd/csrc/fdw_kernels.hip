@@ -567,7 +567,8 @@ hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s)
 }
 
 // Receivers (i, j) -> CSR by row, sorted by (row, column), with validation.  One block; R is
-// at most kMaxReceivers.  status[0] = 0 on success, 1 if a receiver is not an interior node.
+// at most kMaxReceivers.  status[0] = 0 on success, 1 if a receiver is not an interior node;
+// status[1] = number of receivers that share their node with an earlier one in that order.
 __global__ __launch_bounds__(256) void k_receivers_csr(const int* __restrict__ rec, int R, int nx, int ny,
                                                        int* __restrict__ rowptr, int* __restrict__ col,
                                                        int* __restrict__ id, int* status)
@@ -602,7 +603,52 @@ __global__ __launch_bounds__(256) void k_receivers_csr(const int* __restrict__ r
         for (int q = 0; q < R; ++q) c += (rec[2 * q + 1] < y) ? 1 : 0;
         rowptr[y] = c;
     }
-    if (threadIdx.x == 0) status[0] = 0;
+    __shared__ int dups;
+    if (threadIdx.x == 0) dups = 0;
+    __syncthreads();  // col / id complete
+    for (int k = 1 + (int)threadIdx.x; k < R; k += 256) {
+        const int a = id[k], b = id[k - 1];
+        if (rec[2 * a] == rec[2 * b] && rec[2 * a + 1] == rec[2 * b + 1]) atomicAdd(&dups, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        status[0] = 0;
+        status[1] = dups;
+    }
+}
+
+// The stepping kernels record one trace per receiver node (the first receiver of each run of
+// coincident ones in CSR order); copy that column to the other receivers of the run for trace
+// rows lo..hi.
+__global__ void k_trace_dups(char* __restrict__ traces, int es, int R, const int* __restrict__ rec,
+                             const int* __restrict__ id, int64_t lo, int64_t hi)
+{
+    const int64_t total = (hi - lo + 1) * (int64_t)R;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = lo + e / R;
+        const int k = (int)(e % R);
+        if (k == 0) continue;
+        const int a = id[k];
+        int k0 = k;
+        while (k0 > 0 && rec[2 * id[k0 - 1]] == rec[2 * a] && rec[2 * id[k0 - 1] + 1] == rec[2 * a + 1]) --k0;
+        if (k0 == k) continue;
+        const int src = id[k0];
+        char* row = traces + n * (int64_t)R * es;
+        if (es == 8)
+            ((double*)row)[a] = ((const double*)row)[src];
+        else
+            ((float*)row)[a] = ((const float*)row)[src];
+    }
+}
+hipError_t launch_trace_dups(void* traces, int es, int R, const int* rec_ij, const int* id, int64_t lo, int64_t hi,
+                             hipStream_t s)
+{
+    if (hi < lo || R <= 1) return hipSuccess;
+    const int64_t total = (hi - lo + 1) * (int64_t)R;
+    const int64_t want = (total + 255) / 256;
+    const int blocks = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_trace_dups, dim3(blocks), dim3(256), 0, s, (char*)traces, es, R, rec_ij, id, lo, hi);
+    return hipGetLastError();
 }
 hipError_t launch_receivers_csr(const int* rec_ij, int R, int nx, int ny, int* rowptr, int* col, int* id, int* status,
                                 hipStream_t s)

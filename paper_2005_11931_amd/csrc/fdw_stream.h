@@ -125,6 +125,38 @@ __device__ __forceinline__ int wave_in_block()
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// Wave-uniform copies of a pointer and of a 64-bit integer (scalar registers).
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)v);
+    const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(v >> 32));
+    return (P*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t uniform_i64(int64_t x)
+{
+    const unsigned long long v = (unsigned long long)x;
+    const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)v);
+    const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(v >> 32));
+    return (int64_t)(((unsigned long long)hi << 32) | lo);
+}
+
+// Receiver lists are sorted by (row, column): the first entry of col[lo, hi) whose column is
+// at least x, by bisection over wave-uniform (scalar) loads.  Used to cut a row's receivers down
+// to the columns of one strip.
+__device__ __forceinline__ int lower_bound_col(ConstPtr<int> col, int lo, int hi, int x)
+{
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); give each
@@ -311,6 +343,37 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
 #pragma unroll
     for (int t = 0; t < K; ++t) acc[t] = 0.0;
 
+    // receiver tables (trace mode): read as constant memory, so that their wave-uniform lookups
+    // are scalar loads; items whose own rows hold no receiver skip the trace code entirely
+    const ConstPtr<int> rowptr = (ConstPtr<int>)M.rec_rowptr;
+    const ConstPtr<int> rcol = (ConstPtr<int>)M.rec_col;
+    const ConstPtr<int> rid = (ConstPtr<int>)M.rec_id;
+    const bool item_rec = want_trace && (rowptr[r0] < rowptr[r1]);
+    const int own_lo = strip * Wv;  // first owned column of the strip
+    // trace output, read once into scalar registers: loaded where it is used, these would be
+    // vector loads waited for on the spot, and that wait drains every outstanding row load
+    T* const trace_out = want_trace ? uniform_ptr((T*)M.traces) : nullptr;
+    const int trace_R = want_trace ? __builtin_amdgcn_readfirstlane(M.R) : 0;
+    const int64_t trace_rows = want_trace ? uniform_i64(M.trace_rows) : 0;
+    int RPb[K], RPe[K];  // receiver ranges of the rows in flight (by position modulo K)
+#pragma unroll
+    for (int t = 0; t < K; ++t) RPb[t] = RPe[t] = 0;
+    // Receiver of each lane column in the rows in flight (by position modulo K; -1: none), in a
+    // wave-private slice of LDS.  The level loop then records a trace with one store per lane
+    // and no loop: a loop around vector stores would make the compiler wait for every
+    // outstanding row load before each level.  Coincident receivers keep the first of their
+    // run here; the library copies the others' columns after the call.
+    constexpr int kSlotRows = want_trace ? K : 1;
+    constexpr int kSlotCols = want_trace ? kWaveSize * C : 1;
+    __shared__ int s_slot[kWavesPerBlock][kSlotRows][kSlotCols];
+    const int wib = wave_in_block();
+    if (want_trace && item_rec) {
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+#pragma unroll
+            for (int c = 0; c < C; ++c) s_slot[wib][t][lane * C + c] = -1;
+    }
+
     // r1 - r0 + 2K rows are streamed (rounded up to whole unrolled blocks; rows outside the
     // grid load as zeros and are never stored).
     const int nblk = (r1 - r0 + 2 * K + U - 1) / U;
@@ -416,7 +479,7 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
                     // branch instead of a select per value
 #pragma unroll
                     for (int c = 0; c < C; ++c) nd[c] = fma_t(L[c], colm[c], Dr[t - 1][pr][c]);
-                    if (!rin) {
+                    if (__builtin_expect(!rin, 0)) {
 #pragma unroll
                         for (int c = 0; c < C; ++c) nd[c] = T(0);
                         asm volatile("");
@@ -438,21 +501,34 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
                         // at K >= 3)
                         asm volatile("" : "+v"(eb[t - 1]));
                     }
-                    if (want_trace && rown && rin) {
-                        const ConstPtr<int> rowptr = (ConstPtr<int>)M.rec_rowptr;
-                        const ConstPtr<int> rcol = (ConstPtr<int>)M.rec_col;
-                        const ConstPtr<int> rid = (ConstPtr<int>)M.rec_id;
-                        const int kb = rowptr[r], ke = rowptr[r + 1];
-                        const int64_t row = n0 + t;
-                        if (kb < ke && row < M.trace_rows) {
-                            for (int k = kb; k < ke; ++k) {
-                                const int off = rcol[k] - cb;
-                                if (lane_owned && off >= 0 && off < C) {
-                                    T v = nu[0];
-#pragma unroll
-                                    for (int c = 1; c < C; ++c) v = (off == c) ? nu[c] : v;
-                                    ((T*)M.traces)[row * M.R + rid[k]] = v;
+                    if (want_trace && __builtin_expect(item_rec, 0)) {
+                        // receivers of row r in this strip's owned columns, looked up once when
+                        // the row enters level 1 (none for rows the item does not own or that lie
+                        // on the boundary), and entered in the row's slots
+                        if (t == 1) {
+                            int kb = 0, ke = 0;
+                            if (rown && rin) {
+                                kb = rowptr[r];
+                                ke = rowptr[r + 1];
+                                if (kb < ke) {
+                                    kb = lower_bound_col(rcol, kb, ke, own_lo);
+                                    ke = lower_bound_col(rcol, kb, ke, own_lo + Wv);
                                 }
+                            }
+                            RPb[q] = kb;
+                            RPe[q] = ke;
+                            for (int k = kb; k < ke; ++k) {
+                                const int col = rcol[k];
+                                if ((k == kb || rcol[k - 1] != col) && lane == 0) s_slot[wib][q][col - own_lo + Hx] = rid[k];
+                            }
+                        }
+                        if (RPb[q] < RPe[q]) {
+                            const int64_t row = n0 + t;
+#pragma unroll
+                            for (int c = 0; c < C; ++c) {
+                                const int id = s_slot[wib][q][lane * C + c];
+                                if (id >= 0 && row < trace_rows) trace_out[row * trace_R + id] = nu[c];
+                                if (t == K) s_slot[wib][q][lane * C + c] = -1;
                             }
                         }
                     }

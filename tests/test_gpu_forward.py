@@ -247,7 +247,11 @@ def test_traces_and_misfit_vs_oracle():
     case = I.line_case(n=181, nsteps=333)
     rng = np.random.default_rng(3)
     rec = np.stack([rng.integers(1, 180, 40), rng.integers(1, 180, 40)], axis=1).astype(np.int32)
-    rec[5] = rec[4]  # a duplicated receiver
+    # coincident receivers where the signal is strong (the kernels record one trace per node and
+    # the library copies it to the others of the run): three at the peak of u0, two elsewhere
+    j0, i0 = np.unravel_index(np.argmax(np.abs(case.u0)), case.u0.shape)
+    rec[4] = rec[5] = rec[30] = (i0, j0)
+    rec[7] = rec[6]
     _say("traces")
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
     s.configure(fdw.FDW_CFG_TIME_BLOCK, 4)
@@ -257,11 +261,21 @@ def test_traces_and_misfit_vs_oracle():
     ref = oracle.forward_case(case, receivers=rec)
     trn = tr.cpu().numpy()
     assert np.abs(trn - ref["traces"]).max() <= 1e-12
+    assert np.abs(trn[:, 4]).max() > 0.1 and np.array_equal(trn[:, 4], trn[:, 5])
+    assert np.array_equal(trn[:, 4], trn[:, 30]) and np.array_equal(trn[:, 6], trn[:, 7])
     d = rng.normal(size=trn.shape) * 0.01
     J, g = s.misfit(tr, torch.as_tensor(d, device="cuda"))
     Jref = oracle.misfit(ref["traces"], d)
     assert abs(J.item() - Jref) <= 1e-12 * abs(Jref)
     assert np.abs(g.cpu().numpy() - 2 * (ref["traces"] - d)).max() <= 1e-12
+    s.close()
+    # FP32 storage (two columns per lane, K = 8): the same receivers, FP32 bar
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+    tr = s.record_traces(torch.as_tensor(rec))
+    s.step(333)
+    t32 = tr.cpu().numpy().astype(np.float64)
+    assert np.abs(t32 - ref["traces"]).max() <= 1e-5 * np.abs(ref["traces"]).max()
+    assert np.array_equal(t32[:, 4], t32[:, 5]) and np.array_equal(t32[:, 4], t32[:, 30])
     s.close()
 
 
