@@ -99,7 +99,8 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
     const ConstPtr<int> rcol = (ConstPtr<int>)a.rec_col;
     const ConstPtr<int> rid = (ConstPtr<int>)a.rec_id;
     const ConstPtr<double> tgrad = (ConstPtr<double>)a.trace_grad;
-    const bool any_rec = a.R > 0;
+    // items whose rows (halo included) hold no receiver skip the source code entirely
+    const bool any_rec = a.R > 0 && rowptr[max(r0 - K, 0)] < rowptr[min(r1 + K, ny)];
     const int col_lo = strip * Wv - Hx;  // first column the strip computes
     T* __restrict__ uout = (T*)a.uout;
     T* __restrict__ dout = (T*)a.dout;
@@ -274,12 +275,12 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                 }
                 // Dirichlet rows keep du = mu = 0 (and with them u = lam = 0); the row test is
                 // wave-uniform, and the empty asm keeps it a scalar branch instead of selects
-                if (!rin) {
+                if (__builtin_expect(!rin, 0)) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) nd[c] = nm[c] = T(0);
                     asm volatile("");
                 }
-                if (t == 1 && any_rec) {
+                if (t == 1 && __builtin_expect(any_rec, 0)) {
                     // receivers of row r in the columns this strip computes (halo included:
                     // every copy of a node takes its source), once per row
                     int kb = 0, ke = 0;
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_adjoint(AdjArgs 
                     RPb[q] = kb;
                     RPe[q] = ke;
                 }
-                if (any_rec && rin) {
+                if (__builtin_expect(any_rec && rin && RPb[q] < RPe[q], 0)) {
                     const int kb = RPb[q], ke = RPe[q];
                     for (int k = kb; k < ke; ++k) {
                         const int off = rcol[k] - cb;
