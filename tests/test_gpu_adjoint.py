@@ -211,6 +211,30 @@ def test_adjoint_workload_full_size_fd():
     s.close()
 
 
+def test_adjoint_item_rows_do_not_change_the_gradient():
+    """The reverse sweep's rows per work item (automatic: lengthened at 2048^2 until one launch
+    fits the resident waves) change only the halo recomputation, never the arithmetic of a
+    node: the gradient is the same bit for bit for every item height."""
+    import torch
+
+    fdw = _fdw()
+    case, h_true = I.adjoint_case(nsteps=200)
+    rec = torch.as_tensor(case.receivers)
+    _say("adjoint item rows", case.nx, case.nsteps)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    s.step(case.nsteps)
+    # a seeded trace gradient (sources at the receivers in every step)
+    rng = np.random.default_rng(77)
+    tg = torch.as_tensor(rng.normal(size=(case.nsteps + 1, rec.shape[0])), device="cuda")
+    g_auto = s.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+    assert np.abs(g_auto).max() > 0
+    for S in (16, 24, 40, 96):
+        s.configure(fdw.FDW_CFG_ADJ_SEGMENT_ROWS, S)
+        g = s.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+        assert np.array_equal(g, g_auto), S
+    s.close()
+
+
 @pytest.mark.parametrize("ck", [1, 7, 64])
 def test_recorded_checkpoints_equal_replay(ck):
     """Checkpoints stored by the forward run (with traces and energies on) give the same gradient,
