@@ -147,13 +147,13 @@ def small_bench(fdw, torch, I, steps):
     return dict(us_per_step=dt / case.nsteps * 1e6, K=K)
 
 
-def largest_bench(fdw, torch, I, steps):
-    """The largest single-GPU workload: 16384^2 FP32 bathymetry + delta ridge, 10^4 steps."""
+def largest_bench(fdw, torch, I, steps, warmup=1):
+    """The largest single-GPU workload: 16384^2 FP32 bathymetry + delta ridge, 10^4 steps;
+    then the FP32 adjoint on its central 4096^2 crop."""
     n, nsteps = 16384, 10000
     case = I.bathymetry_case(n=n, nsteps=nsteps)
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
     h = torch.as_tensor(case.h1, dtype=torch.float32, device="cuda")
-    del case
     updates = (n - 2) * (n - 2) * nsteps
 
     def one():
@@ -169,7 +169,10 @@ def largest_bench(fdw, torch, I, steps):
     dt = (time.perf_counter() - t0) / max(1, steps)
     K = s.config(fdw.FDW_CFG_TIME_BLOCK)
     s.close()
-    return dict(ups=updates / dt, sec=dt, K=K)
+    del h
+    torch.cuda.empty_cache()
+    crop = adjoint_crop_bench(fdw, torch, I, case, max(1, steps), warmup)
+    return dict(ups=updates / dt, sec=dt, K=K, crop=crop)
 
 
 def family_bench(fdw, torch, I, steps, warmup, persistent=False):
@@ -203,22 +206,46 @@ def family_bench(fdw, torch, I, steps, warmup, persistent=False):
 
 
 def adjoint_bench(fdw, torch, I, steps, warmup):
+    """2048^2 FP64 receiver-misfit gradient: observed traces under h_true, then the misfit and
+    its adjoint at h = h_eps."""
     case, h_true = I.adjoint_case()
     N = case.nsteps
     rec = torch.as_tensor(case.receivers)
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
-    # observed traces under h_true, then the misfit and its adjoint source at h = h_eps
     s.set_coeff(torch.as_tensor(h_true, device="cuda"))
     tr = s.record_traces(rec)
     s.step(N)
     d = tr.clone()
     s.record_traces(None)
-    h = torch.as_tensor(case.h1, device="cuda")
-    s.set_coeff(h)
+    s.set_coeff(torch.as_tensor(case.h1, device="cuda"))
     tr = s.record_traces(rec)
     s.step(N)
     J, tg = s.misfit(tr, d)
     s.record_traces(None)
+    out = _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup)
+    s.close()
+    return out
+
+
+def adjoint_crop_bench(fdw, torch, I, full, steps, warmup):
+    """FP32 adjoint on the central 4096^2 crop of the 16384^2 bathymetry case, 4000 steps, 64
+    receivers, with a seeded trace gradient as the adjoint source."""
+    import numpy as np
+
+    case = I.bathymetry_crop_case(full)
+    N = case.nsteps
+    rec = torch.as_tensor(case.receivers)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+    tg = torch.as_tensor(np.random.default_rng(5004).normal(size=(N + 1, rec.shape[0])), device="cuda")
+    out = _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup)
+    s.close()
+    return out
+
+
+def _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup):
+    """Forward solve, adjoint with its own replay, forward solve recording traces and
+    checkpoints (every 64 steps), adjoint from those checkpoints."""
+    N = case.nsteps
     nb = fdw.lib().fdw_adjoint_workspace_bytes(s.ctx, 0, 64)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     g = torch.empty((case.ny, case.nx), dtype=torch.float64, device="cuda")
@@ -261,9 +288,9 @@ def adjoint_bench(fdw, torch, I, steps, warmup):
     tfr = timed(fwd_rec)
     s.record_traces(None)
     tar = timed(adj_rec)
-    s.close()
     return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, forward_recording_s=tfr, adjoint_recorded_s=tar,
-                ratio_recorded=tar / tf, gradient_ratio=(tfr + tar) / tf, n=case.nx, nsteps=N)
+                ratio_recorded=tar / tf, gradient_ratio=(tfr + tar) / tf, n=case.nx, nsteps=N,
+                grad_max=float(g.abs().max()))
 
 
 def cpu_baseline(I, budget_s=15.0):
@@ -552,11 +579,24 @@ def main():
                         "workload": "256x256 FP64 line singularity h = 1 + 2 phi_0.05(x), 1000 steps with per-step "
                                     "energy, launch sequence replayed from a hipGraph (cache-resident)"}
         log("largest 16384^2 fp32")
-        lg = largest_bench(fdw, torch, I, max(1, args.steps - 2))
+        lg = largest_bench(fdw, torch, I, max(1, args.steps - 2), args.warmup)
+        cr = lg["crop"]
+        log(json.dumps(cr))
         out["largest"] = {"value": round(lg["ups"], 1), "unit": "grid-point updates/s",
                           "ms_per_step": round(lg["sec"] * 1e3, 2), "time_block": lg["K"],
                           "workload": "16384x16384 FP32 smooth random bathymetry 0.2-1 + delta ridge eps = 2 dx, "
-                                      "10000 steps, no energy"}
+                                      "10000 steps, no energy",
+                          "adjoint_crop": {"forward_ms": round(cr["forward_s"] * 1e3, 2),
+                                           "adjoint_ms": round(cr["adjoint_s"] * 1e3, 2),
+                                           "ratio": round(cr["ratio"], 3),
+                                           "forward_recording_ms": round(cr["forward_recording_s"] * 1e3, 2),
+                                           "adjoint_recorded_ms": round(cr["adjoint_recorded_s"] * 1e3, 2),
+                                           "ratio_recorded": round(cr["ratio_recorded"], 3),
+                                           "gradient_ratio": round(cr["gradient_ratio"], 3),
+                                           "workload": "central 4096x4096 crop of the same case (zero Dirichlet "
+                                                       "edge), FP32 state, FP64 gradient, 4000 steps, 64 "
+                                                       "receivers on the row nearest y = 0.075, seeded trace "
+                                                       "gradient, checkpoints every 64 steps"}}
         torch.cuda.empty_cache()
     if not args.skip_cpu:
         log("cpu baseline")

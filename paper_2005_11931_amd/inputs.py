@@ -374,6 +374,40 @@ def bathymetry_case(n: int = 16384, nsteps: int = 10000, cfl: float = 0.5, seeds
                 meta=dict(eps=eps, seeds=list(seeds), hmax=float(h.max()), centres=centres.tolist()))
 
 
+def bathymetry_crop_case(full: Case, first: int = 6144, n: int = 4096, nsteps: int = 4000, nrecv: int = 64,
+                         y_line: float = 0.075, seed: int = 5003, hump_x: float = -0.05,
+                         name: str = "bathymetry_crop") -> Case:
+    """Adjoint workload cut from the largest one: nodes first .. first+n-1 on both axes of the
+    16384^2 bathymetry case (same spacing, same tau), zero Dirichlet data on the crop's edge,
+    nsteps steps, nrecv distinct receivers on the crop row nearest y = y_line (columns seeded).
+    The ridge sets tau (about 1e-6), so in 4000 steps the waves of the parent case's humps
+    travel a few hundredths at most; a hump of width 0.02 at (hump_x, y_line) is added so that
+    the receivers record a signal.
+    """
+    sl = slice(first, first + n)
+    x0 = full.x0 + first * full.dx
+    x1 = full.x0 + (first + n - 1) * full.dx
+    y0 = full.y0 + first * full.dy
+    y1 = full.y0 + (first + n - 1) * full.dy
+    h = np.ascontiguousarray(full.h1[sl, sl])
+    dy = full.dy
+    X, Y = np.meshgrid(x0 + full.dx * np.arange(n), y0 + dy * np.arange(n), indexing="xy")
+    j = int(round((y_line - y0) / dy))
+    u0 = zero_ring(np.ascontiguousarray(full.u0[sl, sl]) + humps(X, Y, [(hump_x, y0 + j * dy)], 0.02))
+    del X, Y
+    rng = np.random.default_rng(seed)
+    cols: List[int] = []
+    seen = set()
+    while len(cols) < nrecv:
+        i = int(rng.integers(1, n - 1))
+        if i not in seen:
+            seen.add(i)
+            cols.append(i)
+    rec = np.array([[i, j] for i in cols], dtype=np.int32)
+    return Case(name, n, n, x0, x1, y0, y1, full.tau, nsteps, h, None, u0, np.zeros_like(u0), receivers=rec,
+                meta=dict(first=first, seed=seed, parent=full.name))
+
+
 # --------------------------------------------------------------------------------------
 # The paper's own experiments (Sections 3.1 - 3.3), on the leapfrog grid
 # --------------------------------------------------------------------------------------
