@@ -188,8 +188,8 @@ enum {
     FDW_CFG_LANE_COLUMNS = 6, /* grid columns per lane of the streaming kernels: 2 or 4 (float), 1 or 2
                                  (double); 0 = default */
     FDW_CFG_ADJ_TIME_BLOCK = 7,  /* reverse steps per launch of the adjoint sweep: 1..6 with 1 (double) or
-                                    2 (float) columns per lane, else 1..4 (0 = 6 for double with 1
-                                    column, else 4) */
+                                    2 (float) columns per lane, else 1..4 (0 = 6 with those lane
+                                    layouts, the defaults, else 4) */
     FDW_CFG_ADJ_LANE_COLUMNS = 8, /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
                                      0 = default (2 for float, 1 for double) */
     FDW_CFG_ADJ_SEGMENT_ROWS = 9  /* rows per work item of the adjoint sweep, 16..4096 (0 = automatic: 4 x the

@@ -667,7 +667,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
     c->dtype = problems[0].dtype;
     c->C = default_cols_per_lane(c->dtype);
     c->adjC = (c->dtype == FDW_F64) ? 1 : 2;
-    c->adjK = (c->dtype == FDW_F64) ? 6 : 4;  // the deepest reverse blocks at two waves per SIMD
+    c->adjK = 6;  // the deepest reverse blocks at two waves per SIMD (the default lane layouts allow it)
     c->stream = (hipStream_t)hip_stream;
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
@@ -1036,7 +1036,7 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         c->C = (int)v;
         break;
     case FDW_CFG_ADJ_TIME_BLOCK:
-        if (v == 0) v = (c->dtype == FDW_F64 && c->adjC == 1) ? 6 : 4;
+        if (v == 0) v = adj_narrow(c->dtype, c->adjC) ? 6 : 4;
         if (v < 1 || v > 6 || (v > 4 && !adj_narrow(c->dtype, c->adjC)))
             return fail(c, FDW_EINVAL, "adjoint time block must be 1..6 (double with 1 column per lane, float with 2) "
                                        "or 1..4");
