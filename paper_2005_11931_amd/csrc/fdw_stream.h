@@ -115,6 +115,9 @@ struct Lanes<double> {
 // instead of waiting behind the outstanding vector loads of the row prefetch.
 template <typename T>
 using ConstPtr = const __attribute__((address_space(4))) T*;
+// Pointer into the global address space: stores through it are global (not flat) stores.
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T*;
 
 // Index of the calling wave in its workgroup, as a wave-uniform (scalar) value.  Written as
 // threadIdx.x / 64 it is a per-lane value to the compiler, and everything derived from it
@@ -351,8 +354,10 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     const bool item_rec = want_trace && (rowptr[r0] < rowptr[r1]);
     const int own_lo = strip * Wv;  // first owned column of the strip
     // trace output, read once into scalar registers: loaded where it is used, these would be
-    // vector loads waited for on the spot, and that wait drains every outstanding row load
-    T* const trace_out = want_trace ? uniform_ptr((T*)M.traces) : nullptr;
+    // vector loads waited for on the spot, and that wait drains every outstanding row load.
+    // The pointer is declared global: a generic (flat) store also counts as an LDS access, so
+    // the next LDS or scalar-load wait would wait for the store to reach memory.
+    GlobalPtr<T> const trace_out = want_trace ? (GlobalPtr<T>)uniform_ptr((T*)M.traces) : nullptr;
     const int trace_R = want_trace ? __builtin_amdgcn_readfirstlane(M.R) : 0;
     const int64_t trace_rows = want_trace ? uniform_i64(M.trace_rows) : 0;
     int RPb[K], RPe[K];  // receiver ranges of the rows in flight (by position modulo K)
