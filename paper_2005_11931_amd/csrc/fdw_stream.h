@@ -651,16 +651,19 @@ __device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
     // The block's stores reach its L2 by the workgroup barrier; one agent-scope release by
     // the arriving thread then writes that L2 back for the other XCDs (the L2 write-back and
     // invalidate act on the whole cache, so one per block is enough) ...
+    // The counter operations themselves are relaxed: an acquire on every poll would invalidate
+    // the XCD's L2 under the blocks still computing the time block; the fences around them give
+    // the ordering (a release fence before the arrival, one acquire fence after the wait).
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const int arrived = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             long spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1L << 26)) {
                     __hip_atomic_fetch_or(&bar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
