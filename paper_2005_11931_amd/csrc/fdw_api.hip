@@ -36,7 +36,8 @@ inline size_t plane_alloc(int ld, int ny, size_t es)
 inline void* plane_origin(void* base, int ld, size_t es) { return (char*)base + (size_t)kPadRowsTop * ld * es; }
 inline size_t elem_size(int dtype) { return dtype == FDW_F32 ? 4 : 8; }
 inline int pitch_of(int nx) { return (int)align_up((size_t)nx, 64); }
-constexpr int kMinSegRows = 16;
+constexpr int kMinSegRows = 8;      // rows per streaming work item, at least
+constexpr int kMinAdjSegRows = 16;  // ... and per reverse-sweep work item
 
 struct HostMember {
     fdw_problem p;
@@ -198,7 +199,7 @@ int choose_S(const fdw_ctx* c)
     // Segments of 16 K rows (the 2K halo rows of a segment are then 1/8 of it, and half of
     // them are usually shared with the neighbouring segment through L2), but short enough to
     // give about 4600 streaming waves (one and a half rounds of the wave slots) for the
-    // largest member; at least 16 rows.
+    // largest member; at least 8 rows (small grids: more, shorter items).
     const int K = choose_K(c);
     int best = kMinSegRows;
     for (const HostMember& hm : c->m) {
@@ -1010,7 +1011,7 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         c->K_cfg = (int)v;
         break;
     case FDW_CFG_SEGMENT_ROWS:
-        if (v != 0 && (v < kMinSegRows || v > 4096)) return fail(c, FDW_EINVAL, "segment rows must be 0 or 16..4096");
+        if (v != 0 && (v < kMinSegRows || v > 4096)) return fail(c, FDW_EINVAL, "segment rows must be 0 or 8..4096");
         c->S_cfg = (int)v;
         c->S_eff = choose_S(c);
         break;
@@ -1051,7 +1052,7 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         c->adjC = (int)v;
         break;
     case FDW_CFG_ADJ_SEGMENT_ROWS:
-        if (v != 0 && (v < kMinSegRows || v > 4096)) return fail(c, FDW_EINVAL, "segment rows must be 0 or 16..4096");
+        if (v != 0 && (v < kMinAdjSegRows || v > 4096)) return fail(c, FDW_EINVAL, "adjoint segment rows must be 0 or 16..4096");
         c->adjS_cfg = (int)v;
         break;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
@@ -1127,8 +1128,8 @@ template <typename T>
 int choose_adj_S(const fdw_ctx* c, const HostMember& hm, int K, bool split)
 {
     if (c->adjS_cfg > 0) return c->adjS_cfg;
-    const int cap = std::max(kMinSegRows, (int)align_up((size_t)hm.ny, 8));
-    const int S0 = std::min(std::max(kMinSegRows, (4 * K + 7) / 8 * 8), cap);
+    const int cap = std::max(kMinAdjSegRows, (int)align_up((size_t)hm.ny, 8));
+    const int S0 = std::min(std::max(kMinAdjSegRows, (4 * K + 7) / 8 * 8), cap);
     const int resident = adjoint_resident_waves<T>(K, c->adjC, hm.face != 0, split);
     AdjArgs a;
     adj_decompose(c, hm, K, S0, a);
@@ -1443,7 +1444,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
             for (int K = 1; K <= 4; ++K) CK.push_back({2, K});
             for (int K = 1; K <= 8; ++K) CK.push_back({1, K});
         }
-        const int Ss[] = {16, 32, 64, 128};
+        const int Ss[] = {8, 16, 32, 64, 128};
         const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode, saveC = c->C;
         c->use_graph = 0;
         c->batch_mode = 0;
