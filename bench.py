@@ -470,8 +470,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
-              "(the sharding design is described in the design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np  # noqa: F401
