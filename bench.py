@@ -98,9 +98,28 @@ def forward_bench(fdw, torch, I, dtype, steps, warmup, n=8192, nsteps=5000):
     K = s.config(fdw.FDW_CFG_TIME_BLOCK)
     S = s.config(fdw.FDW_CFG_SEGMENT_ROWS)
     s.configure(fdw.FDW_CFG_TIMING, 0)
+    s._check(fdw.lib().fdw_get_state(s.ctx, 0, fdw._ptr(snap), None, None))
+    final = snap.cpu().numpy()
     s.close()
     return dict(sec=dt, updates=updates, ups=updates / dt, drift=drift, kernel_ms=ms, launches=launches, K=K, S=S,
-                n=n, nsteps=nsteps)
+                n=n, nsteps=nsteps, final=final)
+
+
+def gpu_state_after(fdw, I, case, dtype, k):
+    """Field u^k of `case` computed on the GPU in storage `dtype` (host FP64 array)."""
+    import numpy as np
+
+    s = fdw.solver_for_case(case, dtype=dtype)
+    s.step(k)
+    u = s.get_state()[0].cpu().numpy().astype(np.float64)
+    s.close()
+    return u
+
+
+def rel_err(a, ref):
+    import numpy as np
+
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
 
 
 def copy_bench(torch, nbytes=1 << 30, reps=5):
@@ -147,9 +166,13 @@ def small_bench(fdw, torch, I, steps):
     return dict(us_per_step=dt / case.nsteps * 1e6, K=K)
 
 
-def largest_bench(fdw, torch, I, steps, warmup=1):
+def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
     """The largest single-GPU workload: 16384^2 FP32 bathymetry + delta ridge, 10^4 steps;
-    then the FP32 adjoint on its central 4096^2 crop."""
+    then the FP32 adjoint on its central 4096^2 crop.  With parity: the FP32 field against the
+    FP64 oracle after a bounded number of steps, and against the FP64 GPU solve over the
+    whole horizon."""
+    import numpy as np
+
     n, nsteps = 16384, 10000
     case = I.bathymetry_case(n=n, nsteps=nsteps)
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
@@ -168,11 +191,31 @@ def largest_bench(fdw, torch, I, steps, warmup=1):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(1, steps)
     K = s.config(fdw.FDW_CFG_TIME_BLOCK)
-    s.close()
-    del h
+    par = {}
+    if parity:
+        u32 = s.get_state()[0].cpu().numpy()
+        s.close()
+        del h
+        torch.cuda.empty_cache()
+        u64 = gpu_state_after(fdw, I, case, fdw.FDW_F64, nsteps)
+        par["fp32_vs_fp64_gpu_full"] = rel_err(u32.astype(np.float64), u64)
+        del u32, u64
+        torch.cuda.empty_cache()
+        import oracle
+
+        k = 100
+        t0 = time.perf_counter()
+        ref = oracle.forward_case(case, nsteps=k)["u_cur"]
+        par["oracle_s"] = round(time.perf_counter() - t0, 2)
+        par["vs_oracle_step"] = k
+        par["fp32_vs_fp64_oracle"] = rel_err(gpu_state_after(fdw, I, case, fdw.FDW_F32, k), ref)
+        del ref
+    else:
+        s.close()
+        del h
     torch.cuda.empty_cache()
-    crop = adjoint_crop_bench(fdw, torch, I, case, max(1, steps), warmup)
-    return dict(ups=updates / dt, sec=dt, K=K, crop=crop)
+    crop = adjoint_crop_bench(fdw, torch, I, case, max(1, steps), warmup, parity=parity)
+    return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par)
 
 
 def family_bench(fdw, torch, I, steps, warmup, persistent=False):
@@ -227,9 +270,10 @@ def adjoint_bench(fdw, torch, I, steps, warmup):
     return out
 
 
-def adjoint_crop_bench(fdw, torch, I, full, steps, warmup):
+def adjoint_crop_bench(fdw, torch, I, full, steps, warmup, parity=True):
     """FP32 adjoint on the central 4096^2 crop of the 16384^2 bathymetry case, 4000 steps, 64
-    receivers, with a seeded trace gradient as the adjoint source."""
+    receivers, with a seeded trace gradient as the adjoint source.  With parity: the FP32
+    gradient against the FP64 gradient of the same crop and source, computed on the GPU."""
     import numpy as np
 
     case = I.bathymetry_crop_case(full)
@@ -239,6 +283,14 @@ def adjoint_crop_bench(fdw, torch, I, full, steps, warmup):
     tg = torch.as_tensor(np.random.default_rng(5004).normal(size=(N + 1, rec.shape[0])), device="cuda")
     out = _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup)
     s.close()
+    if parity:
+        g32 = out.pop("grad")
+        s64 = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+        g64 = s64.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+        s64.close()
+        out["fp32_grad_vs_fp64_gpu"] = rel_err(g32, g64)
+        out["fp32_grad_vs_fp64_gpu_l2"] = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    out.pop("grad", None)
     return out
 
 
@@ -290,13 +342,14 @@ def _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup):
     tar = timed(adj_rec)
     return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, forward_recording_s=tfr, adjoint_recorded_s=tar,
                 ratio_recorded=tar / tf, gradient_ratio=(tfr + tar) / tf, n=case.nx, nsteps=N,
-                grad_max=float(g.abs().max()))
+                grad_max=float(g.abs().max()), grad=g.cpu().numpy())
 
 
 def cpu_baseline(I, budget_s=15.0):
     """The FP64 oracle on the host cores: first k steps of the same 8192^2 workload, k chosen
     from two calibration runs (3 and 13 steps; their difference removes the per-call set-up)
-    so that the timed run takes about budget_s seconds."""
+    so that the timed run takes about budget_s seconds.  Also returns the oracle's u^k, which
+    the GPU states at the same step are compared with."""
     import oracle
 
     n = 8192
@@ -312,12 +365,46 @@ def cpu_baseline(I, budget_s=15.0):
     setup = max(t3 - 3 * per_step, 0.0)
     k = max(4, int((budget_s - setup) / per_step))
     t0 = time.perf_counter()
-    oracle.forward_case(case, nsteps=k)
+    ref = oracle.forward_case(case, nsteps=k)
     dt = time.perf_counter() - t0
     ups = (n - 2) * (n - 2) * k / dt
-    return dict(value=ups, unit="grid-point updates/s", cores=oracle.threads(), kind="oracle",
-                sample=f"FP64 oracle (OpenMP), 8192x8192 point-singularity workload, first {k} of 5000 steps "
-                       f"including input copies ({dt:.1f} s wall)")
+    out = dict(value=ups, unit="grid-point updates/s", cores=oracle.threads(), kind="oracle",
+               sample=f"FP64 oracle (OpenMP), 8192x8192 point-singularity workload, first {k} of 5000 steps "
+                      f"including input copies ({dt:.1f} s wall)", host=host_info())
+    return out, case, k, ref["u_cur"]
+
+
+def host_info():
+    """CPU model, logical CPUs usable by this process and host RAM, from /proc."""
+    model, mem = "unknown", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, cpus=len(os.sched_getaffinity(0)), ram_GiB=round(mem / 2**30, 1))
+
+
+def oracle_single_thread_rate(I, n=2048, steps=20):
+    """The FP64 oracle on one host thread (OMP_NUM_THREADS=1 in a child process), a short
+    sample of a 2048^2 line workload: grid-point updates/s."""
+    import subprocess
+
+    code = ("import sys, time; sys.path.insert(0, %r); import oracle; from paper_2005_11931_amd import inputs as I; "
+            "c = I.line_case(n=%d, nsteps=%d); oracle.forward_case(c, nsteps=2); t = time.perf_counter(); "
+            "oracle.forward_case(c); print((%d - 2) ** 2 * %d / (time.perf_counter() - t))") % (ROOT, n, steps, n, steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    try:
+        return float(r.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return None
 
 
 def profile_run(dtype_name: str):
@@ -473,7 +560,7 @@ def main():
         print("bench.py runs on one GPU only: the solver has no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np  # noqa: F401
+    import numpy as np
     import torch
 
     from paper_2005_11931_amd import fdw
@@ -482,6 +569,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log("forward fp32 8192^2 x 5000")
     f32 = forward_bench(fdw, torch, I, fdw.FDW_F32, args.steps, args.warmup)
+    f32_final = f32.pop("final")
     log(json.dumps(f32))
     nodes = f32["n"] * f32["n"]
     K = f32["K"]
@@ -531,11 +619,17 @@ def main():
             "energy_drift": f32["drift"],
         },
         "roofline": roof,
+        "parity": {"point8192": {}},
     }
     if not args.skip_extra:
         log("forward fp64 8192^2 x 5000")
         f64 = forward_bench(fdw, torch, I, fdw.FDW_F64, max(1, args.steps - 1), args.warmup)
+        f64_final = f64.pop("final")
         log(json.dumps(f64))
+        # the whole 5000-step horizon: FP32 against the FP64 GPU solve (the oracle covers the
+        # first k steps, see cpu_baseline)
+        out["parity"]["point8192"]["fp32_vs_fp64_gpu_full"] = rel_err(f32_final.astype(np.float64), f64_final)
+        del f64_final
         a64 = 5 * 8 * nodes / (f64["kernel_ms"] / 1e3 / max(f64["launches"], 1)) / 1e9
         out["fp64"] = {"value": round(f64["ups"], 1), "unit": "grid-point updates/s", "ms_per_step": round(
             f64["sec"] * 1e3, 2), "time_block": f64["K"], "kernel_GBs": round(a64, 1),
@@ -557,6 +651,7 @@ def main():
         torch.cuda.empty_cache()
         log("adjoint 2048^2 fp64 x 4000")
         adj = adjoint_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
+        adj.pop("grad", None)
         log(json.dumps(adj))
         out["adjoint"] = {"ratio": round(adj["ratio"], 3), "forward_ms": round(adj["forward_s"] * 1e3, 2),
                           "adjoint_ms": round(adj["adjoint_s"] * 1e3, 2),
@@ -581,6 +676,7 @@ def main():
         lg = largest_bench(fdw, torch, I, max(1, args.steps - 2), args.warmup)
         cr = lg["crop"]
         log(json.dumps(cr))
+        out["parity"]["bathymetry16384"] = lg["parity"]
         out["largest"] = {"value": round(lg["ups"], 1), "unit": "grid-point updates/s",
                           "ms_per_step": round(lg["sec"] * 1e3, 2), "time_block": lg["K"],
                           "workload": "16384x16384 FP32 smooth random bathymetry 0.2-1 + delta ridge eps = 2 dx, "
@@ -592,6 +688,8 @@ def main():
                                            "adjoint_recorded_ms": round(cr["adjoint_recorded_s"] * 1e3, 2),
                                            "ratio_recorded": round(cr["ratio_recorded"], 3),
                                            "gradient_ratio": round(cr["gradient_ratio"], 3),
+                                           "fp32_grad_vs_fp64_gpu": cr.get("fp32_grad_vs_fp64_gpu"),
+                                           "fp32_grad_vs_fp64_gpu_l2": cr.get("fp32_grad_vs_fp64_gpu_l2"),
                                            "workload": "central 4096x4096 crop of the same case (zero Dirichlet "
                                                        "edge), FP32 state, FP64 gradient, 4000 steps, 64 "
                                                        "receivers on the row nearest y = 0.075, seeded trace "
@@ -599,7 +697,22 @@ def main():
         torch.cuda.empty_cache()
     if not args.skip_cpu:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(I)
+        cb, case, k, u_ref = cpu_baseline(I)
+        rate1 = oracle_single_thread_rate(I)
+        if rate1:
+            cb["one_thread_value"] = round(rate1, 1)
+            cb["one_thread_sample"] = "FP64 oracle on 1 thread, 2048x2048 line workload, 20 steps"
+        out["cpu_baseline"] = cb
+        # FP32 and FP64 GPU fields against the FP64 oracle at the oracle's step k
+        u32 = gpu_state_after(fdw, I, case, fdw.FDW_F32, k)
+        e32 = rel_err(u32, u_ref)
+        del u32
+        u64 = gpu_state_after(fdw, I, case, fdw.FDW_F64, k)
+        e64 = float(np.abs(u64 - u_ref).max())
+        del u64, u_ref, case
+        out["parity"]["point8192"].update({"vs_oracle_step": k, "fp32_vs_fp64_oracle": e32,
+                                           "fp64_vs_oracle_maxabs": e64})
+        log("parity at step", k, "fp32 rel", e32, "fp64 max-abs", e64)
     print(json.dumps(out), flush=True)
 
 

@@ -152,6 +152,7 @@ class Solver:
             raise FdwError(st, "fdw_init failed")
         self.ctx = ctx
         self._h = [None] * self.count
+        self._gen = [0] * self.count  # bumped whenever a member's coefficient is set
         self._traces = [None] * self.count
         self._ckpt = None  # (member, ckpt_every, workspace) of an armed checkpoint recording
 
@@ -177,6 +178,7 @@ class Solver:
         h1 = h1.contiguous()
         h2 = None if h2 is None else h2.contiguous()
         self._h[member] = (h1, h2)
+        self._gen[member] += 1
         self._check(_lib.fdw_set_coeff(self.ctx, member, _ptr(h1), _ptr(h2)))
 
     def step(self, n: int, energy: bool = False) -> Optional[torch.Tensor]:
@@ -309,11 +311,11 @@ def solver_for_case(case, dtype: int = FDW_F64, device: str = "cuda:0", flags: i
     return s
 
 
-def family_solver(cases, dtype: int = FDW_F32, device: str = "cuda:0") -> Solver:
+def family_solver(cases, dtype: int = FDW_F32, device: str = "cuda:0", flags: int = 0) -> Solver:
     td = torch_dtype(dtype)
     u0 = [torch.as_tensor(c.u0, dtype=td, device=device) for c in cases]
     u1 = [torch.as_tensor(c.u1, dtype=td, device=device) for c in cases]
-    s = Solver([problem_from_case(c, dtype) for c in cases], u0, u1, device=device)
+    s = Solver([problem_from_case(c, dtype, flags) for c in cases], u0, u1, device=device)
     for m, c in enumerate(cases):
         s.set_coeff(torch.as_tensor(c.h1, dtype=td, device=device),
                     None if c.h2 is None else torch.as_tensor(c.h2, dtype=td, device=device), member=m)
@@ -326,7 +328,9 @@ class FdwMisfit(torch.autograd.Function):
     forward: set the coefficient, run the leapfrog solve recording traces and the adjoint's
     checkpoints, FP64 misfit (libfdw).
     backward: adjoint source 2 (traces - d) * grad_output, reverse leapfrog from the recorded
-    checkpoints (libfdw) -> dL/dh.
+    checkpoints (libfdw) -> dL/dh.  If the solver's coefficient was set again after this
+    loss's forward (another loss on the same solver, a line search), the loss's own depth is
+    set back first and the adjoint replays the forward run from the initial data.
     """
 
     @staticmethod
@@ -334,7 +338,8 @@ class FdwMisfit(torch.autograd.Function):
                 ckpt_every: int = 64):
         p = solver.problems[0]
         N = int(round(p.T / p.tau))
-        solver.set_coeff(h.detach().to(solver.tdtype))
+        hs = h.detach().to(solver.tdtype).clone()
+        solver.set_coeff(hs)
         solver.record_checkpoints(ckpt_every)
         tr = solver.record_traces(receivers)
         solver.step(N)
@@ -343,6 +348,8 @@ class FdwMisfit(torch.autograd.Function):
         ctx.receivers = receivers
         ctx.ckpt = ckpt_every
         ctx.h_dtype = h.dtype
+        ctx.h_solver = hs
+        ctx.gen = solver._gen[0]
         ctx.save_for_backward(g)
         solver.record_traces(None)
         return J
@@ -351,5 +358,9 @@ class FdwMisfit(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         tg = g * grad_out.to(torch.float64)
+        if ctx.solver._gen[0] != ctx.gen:
+            # the solver moved on to another depth: back to this loss's (the adjoint replays)
+            ctx.solver.set_coeff(ctx.h_solver)
+            ctx.gen = ctx.solver._gen[0]
         grad_h = ctx.solver.adjoint(ctx.receivers, tg, ckpt_every=ctx.ckpt)
         return grad_h.to(ctx.h_dtype), None, None, None, None

@@ -477,3 +477,43 @@ def paper_2d_case(eps: float = 0.8, dx: float = 0.05, T: float = 5.0, cfl: float
     return Case("paper2d", n, n, 0.0, 100.0, 0.0, 100.0, T / N, N, H, None, u0, np.zeros_like(u0),
                 meta=dict(eps=eps))
 
+
+
+def consistency_family(n: int = 513, eps_list: Sequence[float] = (0.08, 0.04, 0.02, 0.01, 0.005),
+                       sigma: float = 0.1, amp: float = 1.0, centre=(0.3, 0.0), s0: float = 0.05,
+                       T: float = 0.5, cfl: float = 0.5) -> List[Case]:
+    """Consistency with the classical solution (Section 2.3, Theorem 2.6): a smooth positive
+    depth h = 1 + amp exp(-|x|^2 / (2 sigma^2)) (in W^{1,inf}) and a smooth u0 = exp(-|x - c|^2 /
+    (2 s0^2)), each convolved with the 2D unit-mass Gaussian mollifier of width eps.  Both
+    convolutions have closed forms (Gaussian widths add in quadrature):
+        h_eps  = 1 + amp sigma^2 / (sigma^2 + eps^2) exp(-|x|^2 / (2 (sigma^2 + eps^2))),
+        u0_eps = s0^2 / (s0^2 + eps^2) exp(-|x - c|^2 / (2 (s0^2 + eps^2))).
+    Returns the classical problem (eps = 0, first) followed by one member per eps, all on the
+    same n x n grid of [-1, 1]^2 with one common tau (CFL 0.5 for the largest depth) and
+    horizon T; u1 = 0.
+    """
+    x, y, X, Y = mesh(n, n)
+    dx = 2.0 / (n - 1)
+    r2 = X * X + Y * Y
+    c2 = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2
+    out = []
+    for eps in (0.0,) + tuple(eps_list):
+        sh = sigma * sigma + eps * eps
+        su = s0 * s0 + eps * eps
+        h = 1.0 + amp * (sigma * sigma / sh) * np.exp(-r2 / (2.0 * sh))
+        u0 = zero_ring((s0 * s0 / su) * np.exp(-c2 / (2.0 * su)))
+        out.append((eps, h, u0))
+    hmax = max(float(h.max()) for _, h, _ in out)
+    tau0 = cfl_tau(dx, hmax, cfl)
+    N = int(math.ceil(T / tau0))
+    tau = T / N
+    return [Case(f"consistency{eps}", n, n, -1.0, 1.0, -1.0, 1.0, tau, N, h, None, u0, np.zeros_like(u0),
+                 meta=dict(eps=eps, sigma=sigma, amp=amp, s0=s0)) for eps, h, u0 in out]
+
+
+def paper_case1_eps_sweep(eps_list: Sequence[float] = (0.8, 0.5, 0.2, 0.1, 0.05, 0.02), dx: float = 0.005,
+                          T: float = 5.0) -> List[Case]:
+    """Section 3.1, Case 1 (depth 100 | 10 with a jump at x = 75, Friedrichs-mollified) at the
+    regularisation widths the paper compares at t = 5, in row mode; all members share dx and
+    tau (the depth lies in [10, 100] for every eps)."""
+    return [paper_1d_case("jump", eps=e, dx=dx, T=T) for e in eps_list]

@@ -300,3 +300,75 @@ def test_recorded_checkpoints_batched_member():
                           case_b.u1, case_b.nsteps, case_b.receivers, tg, ckpt_every=16)
     assert np.linalg.norm(g - gref) <= 1e-9 * np.linalg.norm(gref)
     S.close()
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_workload_full_size_vs_oracle():
+    """The 2048^2 FP64, 4000-step receiver-misfit gradient (64 receivers, checkpoints every 64
+    steps) element by element against the oracle's own checkpointed FP64 adjoint of the same
+    loss: the observed traces come from the oracle under h_true, and each side computes its
+    traces at h_eps, its misfit, its adjoint source and its gradient.  Bar: max-abs error of
+    the gradient within 1e-6 of its largest entry (1e-6 relative, element-wise)."""
+    import torch
+
+    fdw = _fdw()
+    case, h_true = I.adjoint_case()
+    N = case.nsteps
+    _say("full-size adjoint vs oracle", case.nx, N)
+    d = oracle.forward(case.nx, case.ny, case.dx, case.dy, case.tau, h_true, None, case.u0, case.u1, N,
+                       receivers=case.receivers)["traces"]
+    ref = oracle.forward_case(case)
+    Jref = oracle.misfit(ref["traces"], d)
+    tg_ref = 2.0 * (ref["traces"] - d)
+    _say("oracle forward done")
+    gref = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, None, case.u0, case.u1, N,
+                          case.receivers, tg_ref, ckpt_every=64)
+    _say("oracle adjoint done")
+    rec = torch.as_tensor(case.receivers)
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+    s.record_checkpoints(64)
+    tr = s.record_traces(rec)
+    s.step(N)
+    J, tg = s.misfit(tr, torch.as_tensor(d, device="cuda"))
+    s.record_traces(None)
+    g = s.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+    s.close()
+    err_tr = float(np.abs(tr.cpu().numpy() - ref["traces"]).max())
+    err_J = abs(J.item() - Jref) / abs(Jref)
+    err_g = float(np.abs(g - gref).max() / np.abs(gref).max())
+    err_g2 = float(np.linalg.norm(g - gref) / np.linalg.norm(gref))
+    _say("traces max-abs", err_tr, "J rel", err_J, "grad max-abs rel", err_g, "grad L2 rel", err_g2)
+    assert err_tr <= 1e-12
+    assert err_J <= 1e-10
+    assert err_g <= 1e-6
+
+
+def test_fdw_misfit_two_losses_backward_of_the_first():
+    """Two FdwMisfit losses on one solver at different depths, then the backward of the first:
+    its gradient must be the one at its own depth (the solver is set back to it), as the
+    oracle's adjoint gives it."""
+    import torch
+
+    fdw = _fdw()
+    case, d = _problem(nx=64, ny=64, N=80, seed=14)
+    _say("autograd, two losses")
+    p = fdw.problem_from_case(case, fdw.FDW_F64)
+    solver = fdw.Solver([p], [torch.as_tensor(case.u0, device="cuda")], [torch.as_tensor(case.u1, device="cuda")])
+    rec = torch.as_tensor(case.receivers)
+    dd = torch.as_tensor(d, device="cuda")
+    h_a = torch.as_tensor(case.h1, device="cuda").clone().requires_grad_(True)
+    h_b = torch.as_tensor(case.h1 * 1.05, device="cuda").clone().requires_grad_(True)
+    J_a = fdw.FdwMisfit.apply(h_a, solver, rec, dd, 8)
+    J_b = fdw.FdwMisfit.apply(h_b, solver, rec, dd, 8)
+    J_a.backward()
+    ref = oracle.forward_case(case)
+    gref = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, None, case.u0, case.u1, case.nsteps,
+                          case.receivers, 2.0 * (ref["traces"] - d), ckpt_every=8)
+    assert np.linalg.norm(h_a.grad.cpu().numpy() - gref) <= 1e-9 * np.linalg.norm(gref)
+    J_b.backward()
+    cb = I.Case(**{**case.__dict__, "h1": case.h1 * 1.05})
+    refb = oracle.forward_case(cb)
+    grefb = oracle.adjoint(cb.nx, cb.ny, cb.dx, cb.dy, cb.tau, cb.h1, None, cb.u0, cb.u1, cb.nsteps, cb.receivers,
+                           2.0 * (refb["traces"] - d), ckpt_every=8)
+    assert np.linalg.norm(h_b.grad.cpu().numpy() - grefb) <= 1e-9 * np.linalg.norm(grefb)
+    solver.close()

@@ -396,3 +396,30 @@ def test_full_size_sampled_windows():
                 assert np.abs(got - want).max() <= 1e-12, (j, i)
             else:
                 assert np.abs(got - want).max() <= 1e-5 * max(1.0, np.abs(want).max()), (j, i)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_whole_field_vs_oracle():
+    """8192^2 point-singularity workload, whole field after 300 steps in the benchmark's launch
+    configuration against the FP64 oracle: FP64 max-abs within 1e-12; FP32 relative error
+    max|u32 - u64| / max|u64| within 1e-5 (reported)."""
+    import torch
+
+    fdw = _fdw()
+    n, k = 8192, 300
+    case = I.point_case(n=n, nsteps=5000)
+    _say("whole field vs oracle: oracle", k, "steps")
+    ref = oracle.forward_case(case, nsteps=k)["u_cur"]
+    errs = {}
+    for dt, name in ((fdw.FDW_F64, "f64"), (fdw.FDW_F32, "f32")):
+        s = fdw.solver_for_case(case, dtype=dt)
+        s.step(k)
+        u = s.get_state()[0].cpu().numpy().astype(np.float64)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        errs[name] = float(np.abs(u - ref).max())
+    scale = float(np.abs(ref).max())
+    _say("max-abs f64", errs["f64"], "f32 relative", errs["f32"] / scale)
+    assert errs["f64"] <= 1e-12
+    assert errs["f32"] <= 1e-5 * scale

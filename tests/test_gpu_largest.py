@@ -13,14 +13,21 @@ from paper_2005_11931_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def test_bathymetry_16384_windows_and_energy():
+@pytest.fixture(scope="module")
+def bathymetry():
+    case = I.bathymetry_case(n=16384, nsteps=10000)
+    print("largest: inputs ready", flush=True)
+    return case
+
+
+@pytest.mark.timeout(600)
+def test_bathymetry_16384_windows_and_energy(bathymetry):
     import torch
 
     from paper_2005_11931_amd import fdw
 
     n = 16384
-    case = I.bathymetry_case(n=n, nsteps=10000)
-    print("largest: inputs ready", flush=True)
+    case = bathymetry
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
     n0 = 10
     s.step(n0)
@@ -51,3 +58,32 @@ def test_bathymetry_16384_windows_and_energy():
     print("largest: energy drift over 600 steps", drift, flush=True)
     assert drift < 1e-4
     s.close()
+
+
+@pytest.mark.timeout(600)
+def test_bathymetry_crop_gradient_vs_oracle(bathymetry):
+    """The adjoint workload cut from the largest one (central 4096^2 crop, zero Dirichlet edge,
+    64 receivers, seeded trace gradient, checkpoints every 64 steps) at a shortened horizon of
+    300 steps: the FP64 GPU gradient against the oracle's FP64 adjoint (1e-9 relative), and the
+    FP32 GPU gradient's error against the same oracle gradient, reported and bounded."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+
+    crop = I.bathymetry_crop_case(bathymetry, nsteps=300)
+    N = crop.nsteps
+    rec = torch.as_tensor(crop.receivers)
+    tg = np.random.default_rng(5004).normal(size=(N + 1, len(crop.receivers)))
+    print("crop gradient: oracle", flush=True)
+    gref = oracle.adjoint(crop.nx, crop.ny, crop.dx, crop.dy, crop.tau, crop.h1, None, crop.u0, crop.u1, N,
+                          crop.receivers, tg, ckpt_every=64)
+    scale = np.abs(gref).max()
+    errs = {}
+    for dt, name in ((fdw.FDW_F64, "f64"), (fdw.FDW_F32, "f32")):
+        s = fdw.solver_for_case(crop, dtype=dt)
+        g = s.adjoint(rec, torch.as_tensor(tg), ckpt_every=64).cpu().numpy()
+        s.close()
+        errs[name] = (float(np.abs(g - gref).max() / scale), float(np.linalg.norm(g - gref) / np.linalg.norm(gref)))
+    print("crop gradient errors (max-abs rel, L2 rel):", errs, flush=True)
+    assert errs["f64"][0] <= 1e-9
+    assert errs["f32"][0] <= 1e-3
