@@ -59,6 +59,10 @@ def _load():
             lib.fdwref_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            _DP, _DP, _DP, _DP, ctypes.c_long, _DP, ctypes.c_int, _IP, _DP, _DP, _DP]
             lib.fdwref_forward.restype = ctypes.c_int
+            lib.fdwref_forward_ld.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_long, ctypes.c_int, _IP,
+                                              _DP, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _DP, _DP, _DP]
+            lib.fdwref_forward_ld.restype = ctypes.c_int
             lib.fdwref_misfit.argtypes = [ctypes.c_long, ctypes.c_int, _DP, _DP]
             lib.fdwref_misfit.restype = ctypes.c_double
             lib.fdwref_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -153,6 +157,41 @@ def forward_case(case, nsteps: Optional[int] = None, want_energy: bool = False, 
     rec = case.receivers if receivers is None else receivers
     return forward(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, case.h2, case.u0, case.u1, n,
                    want_energy=want_energy, receivers=rec)
+
+
+def forward_ld(nx: int, ny: int, dx: float, dy: float, tau: float, h1, h2, u0, u1, nsteps: int,
+               receivers: Optional[np.ndarray] = None, marks=()):
+    """The forward definition evaluated in x87 extended precision (long double); results
+    rounded to FP64.  Returns dict(u_prev, u_cur, traces, marks) with marks[k] = u^k for each
+    requested step k <= nsteps."""
+    h1 = _f64(h1)
+    h2 = h1 if h2 is None else _f64(h2)
+    u0, u1 = _f64(u0), _f64(u1)
+    assert h1.shape == (ny, nx) and h2.shape == (ny, nx) and u0.shape == (ny, nx) and u1.shape == (ny, nx)
+    R = 0 if receivers is None else int(len(receivers))
+    rec = tr = None
+    if R:
+        rec = np.ascontiguousarray(receivers, dtype=np.int32)
+        tr = np.empty((nsteps + 1, R))
+    up = np.empty((ny, nx))
+    uc = np.empty((ny, nx))
+    mk = np.ascontiguousarray(sorted(set(int(k) for k in marks)), dtype=np.int64)
+    assert mk.size == 0 or (mk[0] >= 0 and mk[-1] <= nsteps)
+    mo = np.empty((mk.size, ny, nx)) if mk.size else None
+    rc = _load().fdwref_forward_ld(nx, ny, dx, dy, tau, _d(h1), _d(h2), _d(u0), _d(u1), int(nsteps), R,
+                                   None if rec is None else rec.ctypes.data_as(_IP), _d(tr), int(mk.size),
+                                   mk.ctypes.data_as(ctypes.POINTER(ctypes.c_long)) if mk.size else None,
+                                   None if mo is None else mo.ctypes.data_as(_DP), _d(up), _d(uc))
+    if rc != 0:
+        raise ValueError(f"fdwref_forward_ld failed ({rc})")
+    return dict(u_prev=up, u_cur=uc, traces=tr, marks={int(k): mo[q] for q, k in enumerate(mk)})
+
+
+def forward_case_ld(case, nsteps: Optional[int] = None, receivers=None, marks=()):
+    n = case.nsteps if nsteps is None else nsteps
+    rec = case.receivers if receivers is None else receivers
+    return forward_ld(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, case.h2, case.u0, case.u1, n,
+                      receivers=rec, marks=marks)
 
 
 def misfit(traces: np.ndarray, d: np.ndarray) -> float:

@@ -419,3 +419,114 @@ done:
     free(lam_a); free(lam_b); free(lam_c); free(tmp); free(scr); free(levels); free(ckpt);
     return rc;
 }
+
+/* ------------------------------------------------------------------------------------------
+ * The same forward definition (faces, flux-form operator, Taylor start, three-level leapfrog)
+ * evaluated in x87 extended precision (long double, 64-bit significand).  With very small
+ * time steps the three-level form loses accuracy to its own rounding: the rounding of every
+ * u^{n+1} acts on the following steps like a kick to the velocity (u^{n+1} - u^n)/tau, so
+ * those errors add up faster than linearly in n.  This evaluation is the reference that both
+ * FP64 computations (this oracle's and the GPU's) are measured against in that regime; its
+ * own rounding is 2^11 times finer than FP64's.
+ * ------------------------------------------------------------------------------------------ */
+typedef long double ld_t;
+
+static void ld_apply(int nx, int ny, ld_t dx2, ld_t dy2, const ld_t* hx, const ld_t* hy, const ld_t* v, ld_t* out)
+{
+    int j, i;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (j = 0; j < ny; ++j) {
+        for (i = 0; i < nx; ++i) {
+            if (i == 0 || j == 0 || i == nx - 1 || j == ny - 1) {
+                AT(out, j, i) = 0.0L;
+                continue;
+            }
+            ld_t c = AT(v, j, i);
+            ld_t east = AT(hx, j, i) * (AT(v, j, i + 1) - c);
+            ld_t west = AT(hx, j, i - 1) * (AT(v, j, i - 1) - c);
+            ld_t north = AT(hy, j, i) * (AT(v, j + 1, i) - c);
+            ld_t south = AT(hy, j - 1, i) * (AT(v, j - 1, i) - c);
+            AT(out, j, i) = (east + west) / dx2 + (north + south) / dy2;
+        }
+    }
+}
+
+int fdwref_forward_ld(int nx, int ny, double dx, double dy, double tau, const double* h1, const double* h2,
+                      const double* u0, const double* u1, long nsteps, int nrecv, const int* recv, double* traces,
+                      int nmarks, const long* marks, double* mark_out, double* u_prev_out, double* u_cur_out)
+{
+    if (nx < 3 || ny < 3 || !(tau > 0.0) || nsteps < 0 || !h1 || !h2 || !u0 || !u1) return -1;
+    if (check_receivers(nx, ny, nrecv, recv)) return -1;
+    if (nmarks < 0 || (nmarks > 0 && (!marks || !mark_out))) return -1;
+    const size_t n = (size_t)nx * (size_t)ny;
+    ld_t* hx = (ld_t*)malloc(sizeof(ld_t) * n);
+    ld_t* hy = (ld_t*)malloc(sizeof(ld_t) * n);
+    ld_t* a = (ld_t*)malloc(sizeof(ld_t) * n);
+    ld_t* b = (ld_t*)malloc(sizeof(ld_t) * n);
+    ld_t* c = (ld_t*)malloc(sizeof(ld_t) * n);
+    ld_t* scr = (ld_t*)malloc(sizeof(ld_t) * n);
+    if (!hx || !hy || !a || !b || !c || !scr) {
+        free(hx); free(hy); free(a); free(b); free(c); free(scr);
+        return -2;
+    }
+    const ld_t T = (ld_t)tau, tt = T * T, dx2 = (ld_t)dx * (ld_t)dx, dy2 = (ld_t)dy * (ld_t)dy;
+    int j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            const int ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+            AT(hx, j, i) = (i < nx - 1) ? 0.5L * ((ld_t)AT(h1, j, i) + (ld_t)AT(h1, j, i + 1)) : 0.0L;
+            AT(hy, j, i) = (j < ny - 1) ? 0.5L * ((ld_t)AT(h2, j, i) + (ld_t)AT(h2, j + 1, i)) : 0.0L;
+            AT(a, j, i) = ring ? 0.0L : (ld_t)AT(u0, j, i);
+        }
+    }
+    if (traces)
+        for (int r = 0; r < nrecv; ++r) traces[r] = (double)AT(a, recv[2 * r + 1], recv[2 * r]);
+    /* u^s into every snapshot slot that asks for step s */
+#define LD_MARK(s_, u_)                                                                              \
+    for (int q = 0; q < nmarks; ++q)                                                                 \
+        if (marks[q] == (s_))                                                                        \
+            for (size_t k = 0; k < n; ++k) mark_out[(size_t)q * n + k] = (double)(u_)[k];
+    LD_MARK(0, a)
+    ld_t *prev = a, *cur = a, *next = b;
+    int i;
+    if (nsteps >= 1) {
+        ld_apply(nx, ny, dx2, dy2, hx, hy, a, scr);
+#pragma omp parallel for collapse(2) schedule(static)
+        for (j = 0; j < ny; ++j)
+            for (i = 0; i < nx; ++i) {
+                const int ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+                AT(b, j, i) = ring ? 0.0L : AT(a, j, i) + T * (ld_t)AT(u1, j, i) + 0.5L * tt * AT(scr, j, i);
+            }
+        prev = a;
+        cur = b;
+        next = c;
+        if (traces)
+            for (int r = 0; r < nrecv; ++r) traces[nrecv + r] = (double)AT(cur, recv[2 * r + 1], recv[2 * r]);
+        LD_MARK(1, cur)
+        for (long s = 1; s < nsteps; ++s) {
+            ld_apply(nx, ny, dx2, dy2, hx, hy, cur, scr);
+#pragma omp parallel for collapse(2) schedule(static)
+            for (j = 0; j < ny; ++j)
+                for (i = 0; i < nx; ++i) {
+                    const int ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+                    AT(next, j, i) = ring ? 0.0L : 2.0L * AT(cur, j, i) - AT(prev, j, i) + tt * AT(scr, j, i);
+                }
+            if (traces)
+                for (int r = 0; r < nrecv; ++r)
+                    traces[(size_t)(s + 1) * (size_t)nrecv + r] = (double)AT(next, recv[2 * r + 1], recv[2 * r]);
+            LD_MARK(s + 1, next)
+            ld_t* t = prev;
+            prev = cur;
+            cur = next;
+            next = t;
+        }
+    }
+    for (size_t k = 0; k < n; ++k) {
+        if (u_prev_out) u_prev_out[k] = (double)prev[k];
+        if (u_cur_out) u_cur_out[k] = (double)cur[k];
+    }
+    free(hx); free(hy); free(a); free(b); free(c); free(scr);
+    return 0;
+#undef LD_MARK
+}

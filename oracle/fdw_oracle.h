@@ -49,6 +49,16 @@ int fdwref_forward(int nx, int ny, double dx, double dy, double tau, const doubl
                    const double* u0, const double* u1, long nsteps, double* energy, int nrecv,
                    const int* recv, double* traces, double* u_prev_out, double* u_cur_out);
 
+/* The forward definition of fdwref_forward (faces, operator, start, three-level steps)
+ * evaluated in x87 extended precision (long double, 64-bit significand); inputs are FP64,
+ * outputs are rounded to FP64.  The reference at very small time steps, where the FP64
+ * three-level recurrence accumulates its own rounding faster than linearly in n.
+ * traces (NULL or [nsteps+1][nrecv]), u_prev_out and u_cur_out as in fdwref_forward;
+ * mark_out ([nmarks][ny][nx], may be NULL when nmarks = 0) receives u^{marks[q]}. */
+int fdwref_forward_ld(int nx, int ny, double dx, double dy, double tau, const double* h1, const double* h2,
+                      const double* u0, const double* u1, long nsteps, int nrecv, const int* recv, double* traces,
+                      int nmarks, const long* marks, double* mark_out, double* u_prev_out, double* u_cur_out);
+
 /* Misfit J = sum_{n,r} (traces - d)^2 over [nrows][nrecv]. */
 double fdwref_misfit(long nrows, int nrecv, const double* traces, const double* d);
 

@@ -400,16 +400,22 @@ def test_full_size_sampled_windows():
 
 @pytest.mark.timeout(600)
 def test_full_size_whole_field_vs_oracle():
-    """8192^2 point-singularity workload, whole field after 300 steps in the benchmark's launch
-    configuration against the FP64 oracle: FP64 max-abs within 1e-12; FP32 relative error
-    max|u32 - u64| / max|u64| within 1e-5 (reported)."""
+    """8192^2 point-singularity workload (tau = 1.3e-7), whole field after 300 steps in the
+    benchmark's launch configuration.  At this time step the FP64 three-level recurrence
+    accumulates its own rounding faster than linearly (every rounding of u^{n+1} is a velocity
+    kick of size ulp/tau), so the reference is the oracle's extended-precision evaluation of the
+    same definition; the FP64 oracle's own distance to it is printed.  Bars: FP64 max-abs within
+    1e-12; FP32 relative error max|u32 - u| / max|u| within 1e-5 (reported)."""
     import torch
 
     fdw = _fdw()
     n, k = 8192, 300
     case = I.point_case(n=n, nsteps=5000)
-    _say("whole field vs oracle: oracle", k, "steps")
-    ref = oracle.forward_case(case, nsteps=k)["u_cur"]
+    _say("whole field vs oracle: extended-precision oracle", k, "steps")
+    ref = oracle.forward_case_ld(case, nsteps=k)["u_cur"]
+    ref64 = oracle.forward_case(case, nsteps=k)["u_cur"]
+    err_oracle64 = float(np.abs(ref64 - ref).max())
+    del ref64
     errs = {}
     for dt, name in ((fdw.FDW_F64, "f64"), (fdw.FDW_F32, "f32")):
         s = fdw.solver_for_case(case, dtype=dt)
@@ -420,6 +426,6 @@ def test_full_size_whole_field_vs_oracle():
         torch.cuda.empty_cache()
         errs[name] = float(np.abs(u - ref).max())
     scale = float(np.abs(ref).max())
-    _say("max-abs f64", errs["f64"], "f32 relative", errs["f32"] / scale)
+    _say("max-abs f64", errs["f64"], "f32 relative", errs["f32"] / scale, "FP64 oracle max-abs", err_oracle64)
     assert errs["f64"] <= 1e-12
     assert errs["f32"] <= 1e-5 * scale

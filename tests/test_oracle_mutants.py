@@ -34,6 +34,13 @@ MUTANTS = {
     "adjoint_drops_second_level": ("2.0 * AT(lam_next, j, i) - AT(lam_next2, j, i)", "2.0 * AT(lam_next, j, i)"),
     "adjoint_nodal_half": ("double g1 = 0.5 * (", "double g1 = 1.0 * ("),
     "adjoint_y_grad_index": ("(AT(u, j + 1, i) - AT(u, j, i)) / (dy * dy)", "(AT(u, j + 1, i) - AT(u, j - 1 + (j == 0), i)) / (dy * dy)"),
+    # the extended-precision evaluation of the forward definition
+    "ld_start_drops_half": ("0.5L * tt * AT(scr, j, i)", "tt * AT(scr, j, i)"),
+    "ld_start_drops_velocity": ("T * (ld_t)AT(u1, j, i)", "0.0L * (ld_t)AT(u1, j, i)"),
+    "ld_step_previous_level": ("2.0L * AT(cur, j, i) - AT(prev, j, i)", "2.0L * AT(cur, j, i) - AT(cur, j, i)"),
+    "ld_apply_dx_dy_swapped": ("(east + west) / dx2 + (north + south) / dy2", "(east + west) / dy2 + (north + south) / dx2"),
+    "ld_faces_hy_from_h1": ("0.5L * ((ld_t)AT(h2, j, i) + (ld_t)AT(h2, j + 1, i))",
+                            "0.5L * ((ld_t)AT(h1, j, i) + (ld_t)AT(h1, j + 1, i))"),
 }
 
 
@@ -95,6 +102,18 @@ def _pins_pass() -> dict:
     except Exception:
         out["p2"] = False
         out["p4"] = False
+    # P8 the extended-precision forward: the same anisotropic eigenmode with velocity at a tiny
+    # time step (sin(theta/2) = tau sqrt(-mu)/2)
+    try:
+        tau8 = 2e-4 * 2.0 / math.sqrt(4 * h1c / ddx**2 + 4 * h2c / ddy**2)
+        th8 = 2.0 * math.asin(tau8 * math.sqrt(-mu) / 2.0)
+        r8 = oracle.forward_ld(nx, ny, ddx, ddy, tau8, np.full((ny, nx), h1c), np.full((ny, nx), h2c), mode,
+                               v * mode, 1500)
+        B8 = tau8 * v / math.sin(th8)
+        expect8 = (math.cos(1500 * th8) + B8 * math.sin(1500 * th8)) * mode
+        out["p8"] = bool(np.abs(r8["u_cur"] - expect8).max() < 1e-13)
+    except Exception:
+        out["p8"] = False
     # P6 adjoint vs central FD, h1 != h2
     rng = np.random.default_rng(2)
     nx, ny, N = 12, 10, 20

@@ -16,6 +16,9 @@ an invariant, a brute-force derivative or a value the paper prints.
      reflection / transmission coefficients.
   P6 adjoint gradient against central finite differences, the Taylor remainder, and the
      store-all vs checkpointed modes (bitwise).
+  P8 the forward definition evaluated in extended precision (the reference at very small
+     time steps): the exact discrete eigenmode at tau = 2e-4 of the stability limit, the
+     FP64 oracle where that one is accurate, and row-mode d'Alembert.
 """
 import math
 
@@ -111,6 +114,61 @@ def test_p2_apply_is_eigen():
     mu = -(1.5 * 4 / dx**2 * math.sin(2 * math.pi / (2 * (nx - 1))) ** 2
            + 0.25 * 4 / dy**2 * math.sin(3 * math.pi / (2 * (ny - 1))) ** 2)
     assert np.abs(Av - mu * mode).max() < 1e-10 * abs(mu)
+
+
+# ----------------------------------------------------------------------------- P8
+
+
+@pytest.mark.parametrize("k,l,v", [(1, 1, 0.0), (2, 3, 1.3)])
+def test_p8_extended_precision_eigenmode_at_tiny_tau(k, l, v):
+    """The forward definition evaluated in extended precision, at a time step 2e-4 of the
+    stability limit (the regime of the point-singularity workload, tau ~ 1e-7): after 4000
+    steps it equals the exact discrete eigenmode (cos n theta + B sin n theta) mode, with
+    sin(theta/2) = tau sqrt(-mu)/2 and B = tau v / sin theta, to FP64 rounding of the output,
+    while the FP64 three-level recurrence is a thousand times further off (its roundings act
+    as velocity kicks and accumulate faster than linearly at such steps)."""
+    nx, ny = 41, 29
+    h1c, h2c = 2.0, 0.7
+    x0, x1, y0, y1, dx, dy, mode, tau, _ = _eigen_case(nx, ny, h1c, h2c, k, l, v, cfl=2e-4)
+    mu = -(h1c * 4.0 / dx**2 * math.sin(k * math.pi / (2 * (nx - 1))) ** 2
+           + h2c * 4.0 / dy**2 * math.sin(l * math.pi / (2 * (ny - 1))) ** 2)
+    theta = 2.0 * math.asin(tau * math.sqrt(-mu) / 2.0)
+    N = 4000
+    h1 = np.full((ny, nx), h1c)
+    h2 = np.full((ny, nx), h2c)
+    B = tau * v / math.sin(theta)
+    expect = (math.cos(N * theta) + B * math.sin(N * theta)) * mode
+    expect_prev = (math.cos((N - 1) * theta) + B * math.sin((N - 1) * theta)) * mode
+    r = oracle.forward_ld(nx, ny, dx, dy, tau, h1, h2, mode, v * mode, N)
+    err_ld = np.abs(r["u_cur"] - expect).max()
+    assert err_ld < 2e-14
+    assert np.abs(r["u_prev"] - expect_prev).max() < 2e-14
+    r64 = oracle.forward(nx, ny, dx, dy, tau, h1, h2, mode, v * mode, N)
+    assert np.abs(r64["u_cur"] - expect).max() > 100 * err_ld
+
+
+def test_p8_extended_precision_matches_fp64_where_fp64_is_accurate():
+    """At an ordinary time step (CFL 0.5) over a few hundred steps the FP64 oracle is accurate;
+    the extended-precision evaluation must agree with it to FP64 rounding, traces included."""
+    case = I.line_case(n=96, nsteps=300)
+    rec = np.array([[10, 48], [70, 20], [48, 48]], dtype=np.int32)
+    a = oracle.forward_case(case, receivers=rec)
+    b = oracle.forward_case_ld(case, receivers=rec)
+    assert np.abs(a["u_cur"] - b["u_cur"]).max() < 1e-14
+    assert np.abs(a["u_prev"] - b["u_prev"]).max() < 1e-14
+    assert np.abs(a["traces"] - b["traces"]).max() < 1e-14
+
+
+def test_p8_extended_precision_row_mode_dalembert():
+    """Row-mode d'Alembert (h2 = 0, Courant number 1) is exact for the extended evaluation too."""
+    n = 101
+    x = I.node_coords(n, 0.0, 1.0)
+    g = np.exp(-((x - 0.37) / 0.05) ** 2) - 0.5 * np.exp(-((x - 0.71) / 0.03) ** 2)
+    g[0] = g[-1] = 0.0
+    dx = x[1] - x[0]
+    case = I.row_mode_case(x, np.full(n, 1.7 * 1.7), g, dx / 1.7, 137)
+    r = oracle.forward_case_ld(case)
+    assert np.abs(r["u_cur"][1] - _dalembert_row(g, 137)).max() < 1e-14
 
 
 # ----------------------------------------------------------------------------- P3
