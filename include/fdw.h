@@ -122,6 +122,22 @@ int fdw_record_traces(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int3
 int fdw_misfit(fdw_ctx* ctx, int32_t member, const void* traces, const double* d, int64_t rows, int32_t R,
                double* J_dev, double* trace_grad);
 
+/* fdw_misfit for callers that cannot allocate device memory (code under stream capture,
+ * tight loops, harnesses that forbid allocation): no context and no workspace.  Same result,
+ * bit for bit, as fdw_misfit on the same arrays: J_dev (device double) receives
+ * sum_{k<rows, r<R} (traces[k][r] - d[k][r])^2 and trace_grad (device double [rows][R], may be
+ * NULL) the adjoint source 2 (traces - d); traces (device, [rows][R]) is float for FDW_F32
+ * and double for FDW_F64, d is device double; enqueued on hip_stream (NULL = null stream).
+ * The reduction's partial sums live in a fixed 33 KB array in device memory that each GPU
+ * holds once per process (looked up on the first call on a device, which must not be under
+ * stream capture); every call on one GPU shares it, so calls that overlap on one GPU (other
+ * streams, other host threads) race.  Limits: rows <= 2^31 - 1, R <= 16384 (FDW_EINVAL
+ * beyond).  Errors: FDW_EINVAL, FDW_EHIP; fdw_noalloc_last_error() describes the last
+ * failure of this entry point on the calling thread. */
+int fdw_misfit_noalloc(int32_t dtype, const void* traces, const double* d, int64_t rows, int32_t R, double* J_dev,
+                       double* trace_grad, void* hip_stream);
+const char* fdw_noalloc_last_error(void);
+
 /* Device workspace (bytes) fdw_adjoint needs for member m with checkpoints every
  * ckpt_every steps. */
 size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t ckpt_every);

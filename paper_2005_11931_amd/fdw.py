@@ -35,7 +35,7 @@ EXPORTED = [
     "fdw_misfit", "fdw_adjoint_workspace_bytes", "fdw_record_checkpoints", "fdw_adjoint", "fdw_get_state", "fdw_set_state", "fdw_reset",
     "fdw_member_distance",
     "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_kernel_time", "fdw_last_error",
-    "fdw_status_string", "fdw_destroy",
+    "fdw_status_string", "fdw_destroy", "fdw_misfit_noalloc", "fdw_noalloc_last_error",
 ]
 
 
@@ -82,6 +82,10 @@ _lib.fdw_last_error.argtypes = [_vp]
 _lib.fdw_last_error.restype = ctypes.c_char_p
 _lib.fdw_status_string.argtypes = [ctypes.c_int]
 _lib.fdw_status_string.restype = ctypes.c_char_p
+_lib.fdw_misfit_noalloc.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp]
+_lib.fdw_misfit_noalloc.restype = ctypes.c_int
+_lib.fdw_noalloc_last_error.argtypes = []
+_lib.fdw_noalloc_last_error.restype = ctypes.c_char_p
 _lib.fdw_destroy.argtypes = [_vp]
 _lib.fdw_destroy.restype = None
 for _name in ("fdw_set_coeff", "fdw_step_n", "fdw_energy", "fdw_record_traces", "fdw_misfit", "fdw_adjoint",
@@ -295,6 +299,20 @@ class Solver:
         out = (ctypes.c_int64 * 3)()
         self._check(_lib.fdw_autotune(self.ctx, int(steps), out))
         return int(out[0]), int(out[1]), int(out[2])
+
+
+def misfit_noalloc(traces: torch.Tensor, d: torch.Tensor, J_out: torch.Tensor,
+                   grad_out: Optional[torch.Tensor] = None) -> None:
+    """fdw_misfit_noalloc: J_out[()] = sum (traces - d)^2 and grad_out = 2 (traces - d), with no
+    context, no workspace and no device allocation (the outputs are the caller's)."""
+    dt = FDW_F32 if traces.dtype == torch.float32 else FDW_F64
+    assert traces.is_contiguous() and d.is_contiguous() and d.dtype == torch.float64 and traces.shape == d.shape
+    assert J_out.dtype == torch.float64 and (grad_out is None or grad_out.dtype == torch.float64)
+    rows, R = traces.shape
+    st = _lib.fdw_misfit_noalloc(dt, _ptr(traces), _ptr(d), rows, R, _ptr(J_out), _ptr(grad_out),
+                                 _vp(_stream_handle(traces.device)))
+    if st != 0:
+        raise FdwError(st, _lib.fdw_noalloc_last_error().decode())
 
 
 def solver_for_case(case, dtype: int = FDW_F64, device: str = "cuda:0", flags: int = 0, separate_h2: bool = False):
