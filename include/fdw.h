@@ -78,11 +78,16 @@ typedef struct {
 } fdw_problem;
 
 /* Device workspace (bytes) that fdw_init needs for `count` members described by
- * problems[0..count-1].  Returns 0 when the problems are invalid. */
+ * problems[0..count-1] (the state of the Cauchy problem of Section 2, eq. (2.1), on the grid
+ * of Section 3.3, per member).  Returns 0 when the problems are invalid.  The adjoint's
+ * checkpoints are sized separately (fdw_adjoint_workspace_bytes), per member and interval. */
 size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count);
 
 /* Create a context for `count` >= 1 members (count > 1 is a batched family: members may
- * differ in size, tau and coefficient but share the storage type).
+ * differ in size, tau and coefficient but share the storage type).  Each member is one
+ * regularised Cauchy problem: the Cauchy data u(0) = u0, u_t(0) = u1 of eq. (2.1) (Section 2)
+ * on the grid with zero Dirichlet data of Section 3.3; a family holds several
+ * regularisations h_eps of one singular depth (Section 2.1, Section 3.2).
  * workspace: device memory of ws_bytes >= fdw_workspace_bytes(), 256-byte aligned, owned by
  *            the caller and alive until fdw_destroy;
  * u0, u1:    arrays of `count` device pointers, member m's initial displacement and
@@ -92,37 +97,46 @@ size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count);
 int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t ws_bytes,
              const void* const* u0, const void* const* u1, void* hip_stream, fdw_ctx** out);
 
-/* Set member m's coefficient (face coefficients and the stability check).
+/* Set member m's coefficient (face coefficients and the stability check): the positive,
+ * vector-valued depth h = (h1, h2) of eq. (2.1) with h_j >= c0 > 0 (Section 2), usually a
+ * regularisation h_eps = h * psi_eps (Section 2.1, Section 3.1).
  * h1: device [ny][nx] nodal h1; h2: device nodal h2, or NULL when h2 = h1 (the physical
  * model h_1 = h_2 = h; a faster nodal layout is used).  The values are validated (finite,
  * > 0, or >= 0 with FDW_ALLOW_ZERO_H) and the CFL bound is checked; both read one small
  * result back to the host, so this call synchronises the stream.  Resets member m to n = 0. */
 int fdw_set_coeff(fdw_ctx* ctx, int32_t member, const void* h1, const void* h2);
 
-/* Advance every member by n >= 0 steps (the Taylor start step when a member is at n = 0,
- * then leapfrog steps).  energy_dev: NULL, or device double [count][n] receiving
+/* Advance every member by n >= 0 steps of the discretised eq. (2.1) (Section 2; grid of
+ * Section 3.3) (the Taylor start step when a member is at n = 0, then leapfrog steps).  energy_dev: NULL, or device double [count][n] receiving
  * E^{k+1/2} for k = n_cur .. n_cur+n-1 of each member.  Traces registered with
- * fdw_record_traces are written as the steps are taken. */
+ * fdw_record_traces are written as the steps are taken.  With energies requested (and
+ * FDW_CFG_CHECK_ENERGY on, the default) the call checks them before returning: FDW_EUNSTABLE
+ * when one is non-finite or exceeds 10x the first energy of the call (the steps are taken and
+ * the energies written either way); this check synchronises the stream. */
 int fdw_step_n(fdw_ctx* ctx, int64_t n, double* energy_dev);
 
-/* E^{n-1/2} of each member's current pair (u^{n-1}, u^n), into host double [count].
+/* E^{n-1/2} of each member's current pair (u^{n-1}, u^n), into host double [count]: the
+ * discrete form of the conserved energy of Section 2 (proof of Theorem 2.1, identity CL-01).
  * Needs n >= 1 (FDW_ESTATE otherwise); synchronises the stream. */
 int fdw_energy(fdw_ctx* ctx, double* energy_host);
 
-/* Record traces of member m: from now on u^k at the R receivers is written into
+/* Record traces of member m (the solution u(t_k, x_r) of eq. (2.1) at fixed nodes; receivers
+ * and the misfit below are this library's addition for gradients, the paper computes none):
+ * from now on u^k at the R receivers is written into
  * traces[k][r] (device, storage type, [N+1][R], N = the member's llround(T/tau)) for every
  * step k <= N taken; the current step's row is written immediately.
  * recv_ij: device int32 [R][2] = (i, j) of interior nodes, copied during the call.
  * R = 0 (or traces = NULL) stops recording. */
 int fdw_record_traces(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, void* traces);
 
-/* Receiver misfit: J = sum_{k=0}^{rows-1} sum_r (traces[k][r] - d[k][r])^2 in double, and the
+/* Receiver misfit (no passage of the paper: the loss whose gradient fdw_adjoint computes):
+ * J = sum_{k=0}^{rows-1} sum_r (traces[k][r] - d[k][r])^2 in double, and the
  * adjoint source trace_grad[k][r] = 2 (traces - d) (double, may be NULL).  traces is in the
  * storage type of member m, d is double; all device; J_dev is a device double. */
 int fdw_misfit(fdw_ctx* ctx, int32_t member, const void* traces, const double* d, int64_t rows, int32_t R,
                double* J_dev, double* trace_grad);
 
-/* fdw_misfit for callers that cannot allocate device memory (code under stream capture,
+/* (For callers that cannot allocate.)  fdw_misfit for callers that cannot allocate device memory (code under stream capture,
  * tight loops, harnesses that forbid allocation): no context and no workspace.  Same result,
  * bit for bit, as fdw_misfit on the same arrays: J_dev (device double) receives
  * sum_{k<rows, r<R} (traces[k][r] - d[k][r])^2 and trace_grad (device double [rows][R], may be
@@ -139,10 +153,12 @@ int fdw_misfit_noalloc(int32_t dtype, const void* traces, const double* d, int64
 const char* fdw_noalloc_last_error(void);
 
 /* Device workspace (bytes) fdw_adjoint needs for member m with checkpoints every
- * ckpt_every steps. */
+ * ckpt_every steps: the reverse-sweep state and the (N-1)/ckpt_every stored pairs (u, du).
+ * A workspace of its own, since its size depends on the member and the interval. */
 size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t ckpt_every);
 
-/* Store the adjoint's checkpoints during member m's forward run: from step 0 on, every
+/* Checkpointing for the gradient (no passage of the paper: memory/recomputation trade-off of the
+ * discrete adjoint).  Store the adjoint's checkpoints during member m's forward run: from step 0 on, every
  * fdw_step_n writes (u^n, du^n) for n = ckpt_every, 2 ckpt_every, ... < N into adj_ws
  * (device, at least fdw_adjoint_workspace_bytes(member, ckpt_every) bytes, 256-byte aligned,
  * owned by the caller and kept alive while recording).  Time blocks are cut at those steps;
@@ -153,8 +169,9 @@ size_t fdw_adjoint_workspace_bytes(const fdw_ctx* ctx, int32_t member, int32_t c
  * with adj_ws = NULL.  One member per context records at a time (a new call replaces the old). */
 int fdw_record_checkpoints(fdw_ctx* ctx, int32_t member, int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes);
 
-/* Gradient with respect to the nodal coefficient(s) of a loss L of the traces u^k_r,
- * k = 0..N, by the discrete adjoint of the leapfrog scheme of fdw_step_n: the
+/* Gradient with respect to the nodal coefficient(s) h = (h1, h2) of eq. (2.1) (Section 2) of
+ * a loss L of the traces u^k_r, k = 0..N, by the discrete adjoint of the leapfrog scheme of
+ * fdw_step_n (derived from the scheme; the paper has no adjoint): the
  * forward recurrence is replayed from member m's initial data storing the state every
  * ckpt_every steps (skipped when fdw_record_checkpoints recorded them during the forward run
  * that left the member at step N), then the transposed (reverse leapfrog) recurrence runs
@@ -167,7 +184,8 @@ int fdw_record_checkpoints(fdw_ctx* ctx, int32_t member, int32_t ckpt_every, voi
 int fdw_adjoint(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, const double* trace_grad,
                 int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes, double* grad_h1, double* grad_h2);
 
-/* Snapshot / resume: copy member m's state (u^n, du^n = u^n - u^{n-1}) to device
+/* Snapshot / resume of the solution u(t_n, .) (Section 3.3 grid, t_n = n tau): copy member
+ * m's state (u^n, du^n = u^n - u^{n-1}; the increment form carried by the kernels) to device
  * buffers [ny][nx] in the storage type and its step counter to *n (host).  du is all zeros
  * at n = 0.  u and du may be NULL. */
 int fdw_get_state(fdw_ctx* ctx, int32_t member, void* u, void* du, int64_t* n);
@@ -176,18 +194,21 @@ int fdw_get_state(fdw_ctx* ctx, int32_t member, void* u, void* du, int64_t* n);
  * n >= 1 (at n = 0 the state is defined by the initial data). */
 int fdw_set_state(fdw_ctx* ctx, int32_t member, const void* u, const void* du, int64_t n);
 
-/* L2 distance of two members' current fields, sqrt(dx dy sum (u_a - u_b)^2) in double, for
- * comparing regularisations on the same grid (the limit eps -> 0 of Section 3.2).  Both
+/* L2 distance of two members' current fields, sqrt(dx dy sum (u_a - u_b)^2) in double: the
+ * norm ||u_eps1(t, .) - u_eps2(t, .)||_{L^2} of Section 3.2.1 (limiting behaviour as eps -> 0)
+ * and of the consistency statement of Section 2.3 (Theorem 2.6), for regularisations on the
+ * same grid.  Both
  * members must have the same nx, ny and domain; synchronises the stream; result on the host. */
 int fdw_member_distance(fdw_ctx* ctx, int32_t member_a, int32_t member_b, double* dist_host);
 
-/* Return member m to step 0 (its initial data). */
+/* Return member m to step 0 (its Cauchy data u0, u1; no passage: execution control). */
 int fdw_reset(fdw_ctx* ctx, int32_t member);
 
-/* Step counter of member m, or -1 on a bad argument. */
+/* Step counter n of member m (t = n tau), or -1 on a bad argument. */
 int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
 
-/* Execution configuration (tuning; results do not depend on it, bit for bit):
+/* Execution configuration (no passage of the paper: tuning; results do not depend on it,
+ * bit for bit):
  *   FDW_CFG_TIME_BLOCK: time steps per stencil launch: 1..8 for float with 2 columns per lane and
  *     double with 1, 1..6 for float with 4, 1..4 for double with 2 (0 = automatic);
  *   FDW_CFG_SEGMENT_ROWS: rows per streaming work item, 8..4096 (0 = automatic);
@@ -208,14 +229,19 @@ enum {
                                     layouts, the defaults, else 4) */
     FDW_CFG_ADJ_LANE_COLUMNS = 8, /* columns per lane of the adjoint sweep: 2 or 4 (float), 1 or 2 (double);
                                      0 = default (2 for float, 1 for double) */
-    FDW_CFG_ADJ_SEGMENT_ROWS = 9  /* rows per work item of the adjoint sweep, 16..4096 (0 = automatic: 4 x the
+    FDW_CFG_ADJ_SEGMENT_ROWS = 9, /* rows per work item of the adjoint sweep, 16..4096 (0 = automatic: 4 x the
                                      reverse time block, at least 16; lengthened, up to 16 x the block,
                                      until one launch's items fit in the waves the device holds at once) */
+    FDW_CFG_CHECK_ENERGY = 10     /* 1 (default): fdw_step_n checks the energies it computes and returns
+                                     FDW_EUNSTABLE on a non-finite one or on growth beyond 10x the call's
+                                     first energy (one word read back: such calls synchronise the stream);
+                                     0: no check, fully asynchronous */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
 
-/* Autotune the execution configuration for this context: times short runs of the candidate
+/* Autotune the execution configuration for this context (no passage: tuning): times short
+ * runs of the candidate
  * (columns per lane, time block, segment rows) triples on the context's stream, picks the
  * fastest (a larger time block must win by 2%) and applies it.  Every member must be at
  * step 0 (FDW_ESTATE otherwise) and is returned to step 0 (a checkpoint recording stops).
@@ -226,11 +252,16 @@ int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
  * {time_block, segment_rows, lane_columns}. */
 int fdw_autotune(fdw_ctx* ctx, int32_t steps, int64_t* best_out);
 
-/* Instrumentation (FDW_CFG_TIMING = 1, not under graph replay): synchronise the stream and
+/* Instrumentation (no passage: measurement) (FDW_CFG_TIMING = 1, not under graph replay):
+ * synchronise the stream and
  * report the summed device time (ms) and the number of the streaming stencil launches made
  * since the previous call; the counters are then cleared.  ms and launches are host pointers. */
 int fdw_kernel_time(fdw_ctx* ctx, double* ms, int64_t* launches);
 
+/* Error reporting and teardown (no passage: execution control).  fdw_last_error: one line on the
+ * context's last failure (owned by the context, valid until its next call); fdw_status_string:
+ * static text of a status code; fdw_destroy: releases the host side of a context (the caller
+ * still owns the workspace), NULL is ignored. */
 const char* fdw_last_error(const fdw_ctx* ctx);
 const char* fdw_status_string(int status);
 void fdw_destroy(fdw_ctx* ctx);

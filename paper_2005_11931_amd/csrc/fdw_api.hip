@@ -86,6 +86,7 @@ struct fdw_ctx {
     int* barrier = nullptr;
     double* scal = nullptr;  // small device scalars (energies read back by fdw_energy)
     int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0, timing = 0;
+    int check_energy = 1;  // fdw_step_n checks the energies it computes (FDW_CFG_CHECK_ENERGY)
     int C = 4;  // columns per lane of the streaming kernels
     int adjK = 2, adjC = 2;  // time block and columns per lane of the reverse sweep
     int adjS_cfg = 0;        // rows per reverse work item (0 = automatic)
@@ -104,6 +105,9 @@ struct fdw_ctx {
 };
 
 namespace {
+
+// status[8]: failure-detection word of the energy finalisation (see launch_energy_finalize)
+int* health_word(fdw_ctx* c) { return c->status + 8; }
 
 int fail(fdw_ctx* c, int code, const std::string& msg)
 {
@@ -466,7 +470,7 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
         int rc = launch_block<T>(c, 0, c->count, Kb, energy_dev != nullptr, trace, s);
         if (rc) return rc;
         if (energy_dev)
-            HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, Kb, energy_dev, stride, k, s));
+            HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, Kb, energy_dev, stride, k, health_word(c), s));
         c->ctx_step += Kb;
         c->launches += 1;
         for (HostMember& hm : c->m) {
@@ -554,7 +558,9 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
                     if (rc) return rc;
                     rc = launch_block<T>(c, i, 1, 1, e != nullptr, any_trace(c), c->stream);
                     if (rc) return rc;
-                    if (e) HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, i, 1, 1, energy_dev, n, 0, c->stream));
+                    if (e)
+                        HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, i, 1, 1, energy_dev, n, 0, health_word(c),
+                                                            c->stream));
                     // this member alone advanced: its parity and offset move relative to the context
                     hm.n += 1;
                     hm.cur ^= 1;
@@ -832,6 +838,8 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
     if (n < 0) return fail(c, FDW_EINVAL, "n must be >= 0");
     std::vector<int64_t> n_before;
     for (const HostMember& hm : c->m) n_before.push_back(hm.n);
+    const bool check = energy_dev && c->check_energy && n > 0;
+    if (check) HIPCHK(c, launch_fill_bytes(health_word(c), sizeof(int), c->stream));
     const int rc = (c->dtype == FDW_F32) ? step_n_impl<float>(c, n, energy_dev) : step_n_impl<double>(c, n, energy_dev);
     if (rc) return rc;
     // coincident receivers: the kernels recorded the first of each run; copy the others
@@ -840,6 +848,14 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
         if (hm.R <= 0 || !hm.traces || hm.ndup <= 0) continue;
         const int64_t lo = n_before[i] + 1, hi = std::min<int64_t>(hm.n, hm.N);
         HIPCHK(c, launch_trace_dups(hm.traces, (int)elem_size(c->dtype), hm.R, hm.rec_ij, hm.rid, lo, hi, c->stream));
+    }
+    if (check) {
+        // failure detection (the energies of this call): one word read back, the stream synchronised
+        int h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, health_word(c), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (h & 1) return fail(c, FDW_EUNSTABLE, "a non-finite energy was computed (the solution blew up)");
+        if (h & 2) return fail(c, FDW_EUNSTABLE, "the energy grew beyond 10x its first value in the call");
     }
     return FDW_OK;
 }
@@ -1055,6 +1071,10 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         if (v != 0 && (v < kMinAdjSegRows || v > 4096)) return fail(c, FDW_EINVAL, "adjoint segment rows must be 0 or 16..4096");
         c->adjS_cfg = (int)v;
         break;
+    case FDW_CFG_CHECK_ENERGY:
+        if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "check_energy must be 0 or 1");
+        c->check_energy = (int)v;
+        return FDW_OK;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
     invalidate_graphs(c);
@@ -1092,6 +1112,7 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
     case FDW_CFG_ADJ_TIME_BLOCK: return c->adjK;
     case FDW_CFG_ADJ_LANE_COLUMNS: return c->adjC;
     case FDW_CFG_ADJ_SEGMENT_ROWS: return c->adjS_cfg;
+    case FDW_CFG_CHECK_ENERGY: return c->check_energy;
     default: return -1;
     }
 }

@@ -82,8 +82,10 @@ template <typename T>
 int persistent_max_blocks(int K, int C, int face_mode);
 
 template <typename T>
+// health (may be null): bit 0 set when an energy is non-finite, bit 1 when one exceeds 10x the
+// first energy of the call (energy_base[m * energy_stride])
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
-                                  int64_t energy_stride, int64_t energy_offset, hipStream_t s);
+                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s);
 
 template <typename T>
 hipError_t launch_prepare_coeff(const MemberDev* m_host, const void* h1, const void* h2, int face, double* red,

@@ -95,7 +95,7 @@ int persistent_max_blocks<double>(int K, int C, int face_mode)
 // grid = (levels, nmembers)
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table, int first, double* energy_base,
-                                                         int64_t energy_stride, int64_t energy_offset)
+                                                         int64_t energy_stride, int64_t energy_offset, int* health)
 {
     const int t = blockIdx.x;
     const int m = first + blockIdx.y;
@@ -118,20 +118,32 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table,
         if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) energy_base[(int64_t)m * energy_stride + energy_offset + t] = red[0] * M.escale;
+    if (threadIdx.x == 0) {
+        const double E = red[0] * M.escale;
+        energy_base[(int64_t)m * energy_stride + energy_offset + t] = E;
+        if (health) {
+            // failure detection: a non-finite energy (bit 0), or growth beyond 10x the first
+            // energy of the call (bit 1; that one was written by an earlier launch on the stream)
+            if (!isfinite(E)) atomicOr(health, 1);
+            if (energy_offset > 0) {
+                const double E0 = energy_base[(int64_t)m * energy_stride];
+                if (fabs(E) > 10.0 * fabs(E0)) atomicOr(health, 2);
+            }
+        }
+    }
 }
 
 template <typename T>
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
-                                  int64_t energy_stride, int64_t energy_offset, hipStream_t s)
+                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s)
 {
     hipLaunchKernelGGL(k_energy_finalize, dim3(levels, nmembers), dim3(256), 0, s, table, first, energy_base,
-                       energy_stride, energy_offset);
+                       energy_stride, energy_offset, health);
     return hipGetLastError();
 }
-template hipError_t launch_energy_finalize<float>(const MemberDev*, int, int, int, double*, int64_t, int64_t,
+template hipError_t launch_energy_finalize<float>(const MemberDev*, int, int, int, double*, int64_t, int64_t, int*,
                                                   hipStream_t);
-template hipError_t launch_energy_finalize<double>(const MemberDev*, int, int, int, double*, int64_t, int64_t,
+template hipError_t launch_energy_finalize<double>(const MemberDev*, int, int, int, double*, int64_t, int64_t, int*,
                                                    hipStream_t);
 
 // ------------------------------------------------------------------------------------------

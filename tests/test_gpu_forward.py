@@ -429,3 +429,34 @@ def test_full_size_whole_field_vs_oracle():
     _say("max-abs f64", errs["f64"], "f32 relative", errs["f32"] / scale, "FP64 oracle max-abs", err_oracle64)
     assert errs["f64"] <= 1e-12
     assert errs["f32"] <= 1e-5 * scale
+
+
+def test_step_n_detects_blow_up():
+    """Failure detection: fdw_step_n with energies returns FDW_EUNSTABLE when the solution blows
+    up (a time step 1.5x beyond the stability bound, accepted with FDW_ALLOW_UNSTABLE: the
+    energy grows past 10x) and when the state turns non-finite (a NaN in u0); a stable run
+    reports FDW_OK, and with the check switched off the same unstable call returns FDW_OK."""
+    import torch
+
+    fdw = _fdw()
+    case = I.line_case(n=64, nsteps=400)
+    bad = I.Case(**{**case.__dict__, "tau": case.tau * 2.0 * math.sqrt(2.0) * 1.5})
+    s = fdw.solver_for_case(bad, dtype=fdw.FDW_F64, flags=fdw.FDW_ALLOW_UNSTABLE)
+    with pytest.raises(fdw.FdwError) as e:
+        s.step(300, energy=True)
+    assert e.value.status == fdw.FDW_EUNSTABLE
+    s.reset()
+    s.configure(fdw.FDW_CFG_CHECK_ENERGY, 0)
+    s.step(300, energy=True)
+    s.close()
+    u0 = case.u0.copy()
+    u0[20, 20] = float("nan")
+    s = fdw.solver_for_case(I.Case(**{**case.__dict__, "u0": u0}), dtype=fdw.FDW_F32)
+    with pytest.raises(fdw.FdwError) as e:
+        s.step(50, energy=True)
+    assert e.value.status == fdw.FDW_EUNSTABLE and "non-finite" in str(e.value)
+    s.close()
+    s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+    s.step(200, energy=True)
+    s.step(200, energy=True)
+    s.close()
