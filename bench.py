@@ -218,22 +218,25 @@ def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
     return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par)
 
 
-def family_bench(fdw, torch, I, steps, warmup, persistent=False):
+def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False):
+    """The 32-member family, 2000 steps each: one launch per time block over all members
+    (persistent=False) or one persistent cooperative launch per call (persistent=True), both
+    replayed from a hipGraph; optionally with the per-step energy of every member."""
     fam = I.family()
     s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
+    s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
     if persistent:
-        s.configure(fdw.FDW_CFG_BATCH_MODE, 1)  # one cooperative launch per step call
-    else:
-        s.configure(fdw.FDW_CFG_USE_GRAPH, 1)  # one launch per time block over all members, in a graph
+        s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
     nsteps = fam[0].nsteps
     updates = sum((c.nx - 2) * (c.ny - 2) * c.nsteps for c in fam)
     bytes_alg = sum(c.nx * c.ny for c in fam) * 5 * 4 * nsteps / s.config(fdw.FDW_CFG_TIME_BLOCK)
     del fam
+    e = torch.empty((s.count, nsteps), dtype=torch.float64, device="cuda") if energy else None
 
     def one():
         for m in range(s.count):
             s.reset(m)
-        s.step(nsteps)
+        s.step_into(nsteps, e)
 
     for _ in range(warmup):
         one()
@@ -244,8 +247,13 @@ def family_bench(fdw, torch, I, steps, warmup, persistent=False):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    drift = None
+    if energy:
+        E = e.cpu().numpy()
+        drift = float(max(abs(E[m] - E[m][0]).max() / E[m][0] for m in range(E.shape[0])))
     s.close()
-    return dict(sec=dt, updates=updates, ups=updates / dt, members=32, K=K, alg_GBs=bytes_alg / dt / 1e9)
+    return dict(sec=dt, updates=updates, ups=updates / dt, members=32, K=K, alg_GBs=bytes_alg / dt / 1e9,
+                energy_drift=drift)
 
 
 def adjoint_bench(fdw, torch, I, steps, warmup):
@@ -638,16 +646,25 @@ def main():
         log("batched family")
         fam = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
         log(json.dumps(fam))
-        famp = family_bench(fdw, torch, I, 1, 1, persistent=True)
+        fame = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup, energy=True)
+        log(json.dumps(fame))
+        famp = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup, persistent=True, energy=True)
         log(json.dumps(famp))
         out["batched"] = {"value": round(fam["ups"], 1), "unit": "grid-point updates/s", "members": 32,
                           "ms_per_step": round(fam["sec"] * 1e3, 2), "time_block": fam["K"],
                           "alg_GBs": round(fam["alg_GBs"], 1), "frac": round(fam["alg_GBs"] / HBM_PEAK_GBS, 4),
-                          "persistent_value": round(famp["ups"], 1),
+                          "energy_value": round(fame["ups"], 1),
+                          "energy_frac": round(fame["alg_GBs"] / HBM_PEAK_GBS, 4),
+                          "persistent_energy_value": round(famp["ups"], 1),
+                          "persistent_energy_frac": round(famp["alg_GBs"] / HBM_PEAK_GBS, 4),
+                          "persistent_energy_ms_per_step": round(famp["sec"] * 1e3, 2),
+                          "energy_drift_max": famp["energy_drift"],
                           "workload": "32 regularisations, eps log-spaced 0.1 .. 2dx, delta line / Heaviside jump, "
                                       "512^2-4096^2, 2000 steps, FP32; value: one launch per time block covering "
-                                      "all members, replayed from a hipGraph; persistent_value: one cooperative "
-                                      "launch per call with a grid barrier between time blocks"}
+                                      "all members, replayed from a hipGraph; energy_value: the same with the "
+                                      "per-step energy of every member; persistent_energy_value: one cooperative "
+                                      "launch per call (grid barrier between time blocks, energies summed in the "
+                                      "launch), replayed from a hipGraph"}
         torch.cuda.empty_cache()
         log("adjoint 2048^2 fp64 x 4000")
         adj = adjoint_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)

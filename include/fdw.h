@@ -57,7 +57,9 @@ enum {
     FDW_ENOMEM = -4,    /* workspace too small */
     FDW_EHIP = -5,      /* a HIP runtime error; see fdw_last_error */
     FDW_EUNSTABLE = -6, /* a non-finite energy was produced */
-    FDW_ENOTSUP = -7    /* configuration not supported */
+    FDW_ENOTSUP = -7,   /* configuration not supported */
+    FDW_ESYNC = -8      /* a grid barrier of the persistent launch timed out: the steps of that call
+                           are not valid (the context must be reset or its state set) */
 };
 
 /* fdw_problem.flags */
@@ -112,7 +114,10 @@ int fdw_set_coeff(fdw_ctx* ctx, int32_t member, const void* h1, const void* h2);
  * fdw_record_traces are written as the steps are taken.  With energies requested (and
  * FDW_CFG_CHECK_ENERGY on, the default) the call checks them before returning: FDW_EUNSTABLE
  * when one is non-finite or exceeds 10x the first energy of the call (the steps are taken and
- * the energies written either way); this check synchronises the stream. */
+ * the energies written either way); this check synchronises the stream.  In batch mode 1 (the
+ * persistent launch) the call also reads back the launch's grid-barrier word (synchronising the
+ * stream) and returns FDW_ESYNC if a barrier wait timed out; traces and checkpoint recording
+ * use the per-time-block launches instead. */
 int fdw_step_n(fdw_ctx* ctx, int64_t n, double* energy_dev);
 
 /* E^{n-1/2} of each member's current pair (u^{n-1}, u^n), into host double [count]: the
@@ -214,8 +219,11 @@ int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
  *   FDW_CFG_SEGMENT_ROWS: rows per streaming work item, 8..4096 (0 = automatic);
  *   FDW_CFG_USE_GRAPH: 1 captures the launch sequence of a step_n call in a hipGraph and
  *     replays it for later calls with the same shape (0 = plain launches);
- *   FDW_CFG_BATCH_MODE: for count > 1, 0 = one launch per time block covering all members,
- *     1 = one persistent cooperative launch per step_n call. */
+ *   FDW_CFG_BATCH_MODE: 0 = one launch per time block covering all members, 1 = one persistent
+ *     cooperative launch per step_n call (up to 8192 steps per launch) with the energies summed
+ *     in the launch; combined with FDW_CFG_USE_GRAPH the launch is replayed from a hipGraph.
+ *     The state is the same bit for bit in both modes; the energies agree to rounding (their
+ *     partial sums are added in a different order). */
 enum {
     FDW_CFG_TIME_BLOCK = 1,
     FDW_CFG_SEGMENT_ROWS = 2,
@@ -232,10 +240,14 @@ enum {
     FDW_CFG_ADJ_SEGMENT_ROWS = 9, /* rows per work item of the adjoint sweep, 16..4096 (0 = automatic: 4 x the
                                      reverse time block, at least 16; lengthened, up to 16 x the block,
                                      until one launch's items fit in the waves the device holds at once) */
-    FDW_CFG_CHECK_ENERGY = 10     /* 1 (default): fdw_step_n checks the energies it computes and returns
+    FDW_CFG_CHECK_ENERGY = 10,    /* 1 (default): fdw_step_n checks the energies it computes and returns
                                      FDW_EUNSTABLE on a non-finite one or on growth beyond 10x the call's
                                      first energy (one word read back: such calls synchronise the stream);
                                      0: no check, fully asynchronous */
+    FDW_CFG_TEST_BARRIER_FLAG = 11 /* test hook: 1 marks the next fdw_step_n as if a grid barrier of the
+                                      persistent launch had timed out (the host writes the error word that
+                                      the call reads back; no kernel waits on it): that call returns
+                                      FDW_ESYNC; the hook then resets itself */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);

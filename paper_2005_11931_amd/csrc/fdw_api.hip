@@ -87,6 +87,8 @@ struct fdw_ctx {
     double* scal = nullptr;  // small device scalars (energies read back by fdw_energy)
     int K_cfg = 0, S_cfg = 0, use_graph = 0, batch_mode = 0, timing = 0;
     int check_energy = 1;  // fdw_step_n checks the energies it computes (FDW_CFG_CHECK_ENERGY)
+    int test_flag_barrier = 0;  // FDW_CFG_TEST_BARRIER_FLAG: mark the next persistent call as timed out
+    bool used_persistent = false;  // the last step_n ran the persistent launch
     int C = 4;  // columns per lane of the streaming kernels
     int adjK = 2, adjC = 2;  // time block and columns per lane of the reverse sweep
     int adjS_cfg = 0;        // rows per reverse work item (0 = automatic)
@@ -106,8 +108,10 @@ struct fdw_ctx {
 
 namespace {
 
-// status[8]: failure-detection word of the energy finalisation (see launch_energy_finalize)
+// status[8]: failure-detection word of the energy finalisation (see launch_energy_finalize);
+// status[9]: error word of the persistent launch (bit 0: a grid barrier timed out)
 int* health_word(fdw_ctx* c) { return c->status + 8; }
+int* sync_err_word(fdw_ctx* c) { return c->status + 9; }
 
 int fail(fdw_ctx* c, int code, const std::string& msg)
 {
@@ -160,7 +164,7 @@ size_t member_bytes(const fdw_problem& p)
     b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);        // rec_ij
     b += align_up(sizeof(int) * (size_t)(p.ny + 1), kAlign);       // rowptr
     b += 2 * align_up(sizeof(int) * kMaxReceivers, kAlign);        // col, id
-    b += align_up(sizeof(double) * kMaxTimeBlock * maxw, kAlign);  // energy partials
+    b += align_up(sizeof(double) * 2 * kMaxTimeBlock * maxw, kAlign);  // energy partials (two slots)
     return b;
 }
 
@@ -490,15 +494,24 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
     return FDW_OK;
 }
 
-template <typename T>
-int run_persistent(fdw_ctx* c, int64_t steps)
+// Time block of the persistent kernel (instantiated for 1, 2, 4, 8).
+int persistent_K(const fdw_ctx* c)
 {
     const int Kc = choose_K(c);
-    const int K = Kc >= 8 ? 8 : (Kc >= 4 ? 4 : (Kc >= 2 ? 2 : 1));  // time blocks of the persistent kernel
+    return Kc >= 8 ? 8 : (Kc >= 4 ? 4 : (Kc >= 2 ? 2 : 1));
+}
+
+// The main loop of step_n as one cooperative launch per kPersistentPhases time blocks (then the
+// remaining steps as ordinary launches).  Energies as in run_blocks: the launch sums the
+// energies of all but its last time block itself; that one is summed by k_energy_finalize.
+template <typename T>
+int run_persistent(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, int64_t koff, hipStream_t s)
+{
+    const int K = persistent_K(c);
     int face_mode = c->m[0].face;
     for (const HostMember& hm : c->m)
         if (hm.face != face_mode) return fail(c, FDW_ENOTSUP, "persistent batch needs one coefficient layout");
-    int rc = layout_for_K(c, K, c->S_eff);
+    int rc = layout_for_K(c, K, c->S_eff, s);
     if (rc) return rc;
     const int64_t phases = steps / K;
     const int64_t tail = steps - phases * K;
@@ -506,10 +519,10 @@ int run_persistent(fdw_ctx* c, int64_t steps)
     for (const MemberDev& md : c->tab) total += md.blocks;
     int grid = std::min(total, persistent_max_blocks<T>(K, c->C, face_mode));
     if (grid < 1) return fail(c, FDW_EHIP, "persistent launch: no resident blocks");
+    int64_t k = koff;
     for (int64_t done = 0; done < phases;) {
-        // one cooperative launch per kPersistentPhases time blocks
         const int ph = (int)std::min<int64_t>(kPersistentPhases, phases - done);
-        HIPCHK(c, launch_fill_bytes(c->barrier, (size_t)(16 + 8 * ph) * sizeof(int), c->stream));
+        HIPCHK(c, launch_fill_bytes(c->barrier, (size_t)kPersistentCtlInts * sizeof(int), s));
         StepArgs a;
         a.table = c->tab_dev;
         a.first = 0;
@@ -517,11 +530,20 @@ int run_persistent(fdw_ctx* c, int64_t steps)
         a.block_offset = 0;
         a.total_blocks = total;
         a.parity = (int)(c->launches & 1);
-        a.want_energy = 0;
+        a.want_energy = energy_dev ? 1 : 0;
         a.want_trace = 0;
         a.ctx_step = c->ctx_step;
         a.stream_nt = stream_nt(c) ? 1 : 0;
-        HIPCHK(c, launch_step_persistent<T>(a, K, c->C, face_mode, ph, grid, c->barrier, c->stream));
+        PersistentExtra x;
+        x.energy_base = energy_dev;
+        x.energy_stride = stride;
+        x.energy_offset = k;
+        x.health = health_word(c);
+        x.err = sync_err_word(c);
+        HIPCHK(c, launch_step_persistent<T>(a, K, c->C, face_mode, ph, grid, c->barrier, x, s));
+        if (energy_dev)
+            HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, K, energy_dev, stride, k + (int64_t)(ph - 1) * K,
+                                                health_word(c), s, (ph - 1) & 1));
         c->ctx_step += (int64_t)ph * K;
         c->launches += ph;
         for (HostMember& hm : c->m) {
@@ -529,9 +551,39 @@ int run_persistent(fdw_ctx* c, int64_t steps)
             if (ph & 1) hm.cur ^= 1;
         }
         done += ph;
+        k += (int64_t)ph * K;
     }
-    if (tail > 0) return run_blocks<T>(c, tail, nullptr, 0, 0, c->stream);
+    if (tail > 0) return run_blocks<T>(c, tail, energy_dev, stride, k, s);
+    if (choose_K(c) != K) return layout_for_K(c, choose_K(c), c->S_eff, s);
     return FDW_OK;
+}
+
+// Host bookkeeping of a replayed launch sequence (what run_blocks / run_persistent update).
+void replay_bookkeeping(fdw_ctx* c, int64_t steps, bool persistent)
+{
+    int64_t l = steps;
+    if (persistent) {
+        const int K = persistent_K(c);
+        const int64_t phases = l / K;
+        c->ctx_step += phases * K;
+        c->launches += phases;
+        for (HostMember& hm : c->m) {
+            hm.n += phases * K;
+            if (phases & 1) hm.cur ^= 1;
+        }
+        l -= phases * K;
+    }
+    const int K = choose_K(c);
+    while (l > 0) {
+        const int Kb = (int)std::min<int64_t>(K, l);
+        c->ctx_step += Kb;
+        c->launches += 1;
+        for (HostMember& hm : c->m) {
+            hm.n += Kb;
+            hm.cur ^= 1;
+        }
+        l -= Kb;
+    }
 }
 
 template <typename T>
@@ -575,19 +627,25 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
     const int64_t left = n - done;
     if (left <= 0) return FDW_OK;
     const bool recording = c->rec.member >= 0;
-    if (c->batch_mode == 1 && energy_dev == nullptr && !any_trace(c) && !recording) return run_persistent<T>(c, left);
+    // traces and checkpoint recording need the per-time-block launches
+    const bool persistent = c->batch_mode == 1 && !any_trace(c) && !recording;
+    c->used_persistent = persistent;
     if (c->use_graph && !any_trace(c) && !recording) {
         // The launch sequence of the main loop depends only on (steps, K, energy pointer and
-        // offset, launch parity); capture it once and replay it.
-        const auto key = std::make_tuple(left, choose_K(c), (const double*)energy_dev, (int)(c->launches & 1),
-                                         (int)done);
+        // offset, launch parity, batch mode); capture it once and replay it.
+        const auto key = std::make_tuple(left, choose_K(c) + 16 * (int)persistent, (const double*)energy_dev,
+                                         (int)(c->launches & 1), (int)done);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            int rc = run_blocks<T>(c, left, energy_dev, n, done, c->cap_stream);
+            int rc = persistent ? run_persistent<T>(c, left, energy_dev, n, done, c->cap_stream)
+                                : run_blocks<T>(c, left, energy_dev, n, done, c->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-            if (rc) return rc;
+            if (rc) {
+                if (g) hipGraphDestroy(g);
+                return rc;
+            }
             if (e != hipSuccess) return fail(c, FDW_EHIP, std::string("capture: ") + hipGetErrorString(e));
             GraphEntry ge;
             e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
@@ -595,23 +653,12 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
             if (e != hipSuccess) return fail(c, FDW_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
             it = c->graphs.emplace(key, ge).first;
         } else {
-            // replay: the same bookkeeping as run_blocks
-            const int K = choose_K(c);
-            int64_t l = left;
-            while (l > 0) {
-                const int Kb = (int)std::min<int64_t>(K, l);
-                c->ctx_step += Kb;
-                c->launches += 1;
-                for (HostMember& hm : c->m) {
-                    hm.n += Kb;
-                    hm.cur ^= 1;
-                }
-                l -= Kb;
-            }
+            replay_bookkeeping(c, left, persistent);
         }
         HIPCHK(c, hipGraphLaunch(it->second.exec, c->stream));
         return FDW_OK;
     }
+    if (persistent) return run_persistent<T>(c, left, energy_dev, n, done, c->stream);
     return run_blocks<T>(c, left, energy_dev, n, done, c->stream);
 }
 
@@ -633,6 +680,7 @@ const char* fdw_status_string(int s)
     case FDW_EHIP: return "HIP runtime error";
     case FDW_EUNSTABLE: return "non-finite energy";
     case FDW_ENOTSUP: return "not supported";
+    case FDW_ESYNC: return "grid barrier timed out";
     default: return "unknown status";
     }
 }
@@ -719,7 +767,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
         hm.rcol = (int*)take(sizeof(int) * kMaxReceivers);
         hm.rid = (int*)take(sizeof(int) * kMaxReceivers);
         hm.epart_stride = max_strips(p.nx) * ((p.ny + kMinSegRows - 1) / kMinSegRows);
-        hm.epart = (double*)take(sizeof(double) * kMaxTimeBlock * (size_t)hm.epart_stride);
+        hm.epart = (double*)take(sizeof(double) * 2 * kMaxTimeBlock * (size_t)hm.epart_stride);
 
         MemberDev& md = c->tab[i];
         std::memset(&md, 0, sizeof(md));
@@ -839,7 +887,11 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
     std::vector<int64_t> n_before;
     for (const HostMember& hm : c->m) n_before.push_back(hm.n);
     const bool check = energy_dev && c->check_energy && n > 0;
-    if (check) HIPCHK(c, launch_fill_bytes(health_word(c), sizeof(int), c->stream));
+    // both words (failure detection, barrier timeout) start at zero; a test can mark the
+    // barrier word as if the persistent launch had timed out (no kernel waits on it)
+    HIPCHK(c, launch_fill_bytes(health_word(c), 2 * sizeof(int), c->stream));
+    if (c->test_flag_barrier) HIPCHK(c, launch_set_int(sync_err_word(c), 1, c->stream));
+    c->used_persistent = false;
     const int rc = (c->dtype == FDW_F32) ? step_n_impl<float>(c, n, energy_dev) : step_n_impl<double>(c, n, energy_dev);
     if (rc) return rc;
     // coincident receivers: the kernels recorded the first of each run; copy the others
@@ -849,13 +901,18 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
         const int64_t lo = n_before[i] + 1, hi = std::min<int64_t>(hm.n, hm.N);
         HIPCHK(c, launch_trace_dups(hm.traces, (int)elem_size(c->dtype), hm.R, hm.rec_ij, hm.rid, lo, hi, c->stream));
     }
-    if (check) {
-        // failure detection (the energies of this call): one word read back, the stream synchronised
-        int h = 0;
-        HIPCHK(c, hipMemcpyAsync(&h, health_word(c), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (check || c->used_persistent || c->test_flag_barrier) {
+        // failure detection (the energies of this call) and the persistent launch's barrier word:
+        // two words read back, the stream synchronised
+        int h[2] = {0, 0};
+        HIPCHK(c, hipMemcpyAsync(h, health_word(c), 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (h & 1) return fail(c, FDW_EUNSTABLE, "a non-finite energy was computed (the solution blew up)");
-        if (h & 2) return fail(c, FDW_EUNSTABLE, "the energy grew beyond 10x its first value in the call");
+        c->test_flag_barrier = 0;
+        if (h[1] & 1)
+            return fail(c, FDW_ESYNC, "a grid barrier of the persistent launch timed out: the steps of this call are "
+                                      "not valid");
+        if (check && (h[0] & 1)) return fail(c, FDW_EUNSTABLE, "a non-finite energy was computed (the solution blew up)");
+        if (check && (h[0] & 2)) return fail(c, FDW_EUNSTABLE, "the energy grew beyond 10x its first value in the call");
     }
     return FDW_OK;
 }
@@ -1075,6 +1132,10 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "check_energy must be 0 or 1");
         c->check_energy = (int)v;
         return FDW_OK;
+    case FDW_CFG_TEST_BARRIER_FLAG:
+        if (v != 0 && v != 1) return fail(c, FDW_EINVAL, "test_barrier_flag must be 0 or 1");
+        c->test_flag_barrier = (int)v;
+        return FDW_OK;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
     invalidate_graphs(c);
@@ -1113,6 +1174,7 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
     case FDW_CFG_ADJ_LANE_COLUMNS: return c->adjC;
     case FDW_CFG_ADJ_SEGMENT_ROWS: return c->adjS_cfg;
     case FDW_CFG_CHECK_ENERGY: return c->check_energy;
+    case FDW_CFG_TEST_BARRIER_FLAG: return c->test_flag_barrier;
     default: return -1;
     }
 }

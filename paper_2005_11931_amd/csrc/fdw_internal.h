@@ -49,7 +49,8 @@ struct MemberDev {
     const int* rec_col;     // [R] column of each receiver, sorted by (row, column)
     const int* rec_id;      // [R] position of the receiver in the caller's list
     void* traces;           // [trace_rows][R]
-    double* epart;          // energy partials [kMaxTimeBlock][max waves]
+    double* epart;          // energy partials [2][kMaxTimeBlock][max waves] (two slots: the persistent
+                            // launch alternates them between time blocks)
     int epart_stride;       // max waves
     int stream_nt;          // 1: the launch's planes exceed the last-level cache; stream them
                             // with non-temporal accesses (0: keep them cacheable)
@@ -70,6 +71,16 @@ struct StepArgs {
     int pad_;
 };
 
+// Extra arguments of the persistent launch: where its energies go (as for
+// launch_energy_finalize) and its error words.
+struct PersistentExtra {
+    double* energy_base;    // energy of member m, step k of the call: energy_base[m * energy_stride + k]
+    int64_t energy_stride;
+    int64_t energy_offset;  // step of the call the launch's first time block starts at
+    int* health;            // failure detection, as for launch_energy_finalize
+    int* err;               // bit 0: a grid barrier timed out (results invalid)
+};
+
 // ---- launchers (fdw_kernels.hip) ---------------------------------------------------------
 // All return hipError_t of the launch.
 // C = columns per lane (float: 2 or 4; double: 2)
@@ -77,15 +88,17 @@ template <typename T>
 hipError_t launch_step(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s);
 template <typename T>
 hipError_t launch_step_persistent(const StepArgs& a, int K, int C, int face_mode, int phases, int grid, int* barrier,
-                                  hipStream_t s);
+                                  const PersistentExtra& x, hipStream_t s);
 template <typename T>
 int persistent_max_blocks(int K, int C, int face_mode);
 
 template <typename T>
 // health (may be null): bit 0 set when an energy is non-finite, bit 1 when one exceeds 10x the
 // first energy of the call (energy_base[m * energy_stride])
+// slot: which of the two partial slots holds the levels (0 except after a persistent launch)
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
-                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s);
+                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s,
+                                  int slot = 0);
 
 template <typename T>
 hipError_t launch_prepare_coeff(const MemberDev* m_host, const void* h1, const void* h2, int face, double* red,
@@ -105,6 +118,7 @@ hipError_t launch_copy_in(const void* src, int nx, int ny, void* dst, int ld, in
 template <typename T>
 hipError_t launch_copy_out(const void* src, int ld, int nx, int ny, void* dst, hipStream_t s);
 hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);  // *p = v, stream-ordered (a kernel, not a memset)
 template <typename T>
 hipError_t launch_diff_norm(const void* a, const void* b, int ld, int nx, int ny, double scale, double* red,
                             double* out, hipStream_t s);

@@ -33,13 +33,13 @@ hipError_t launch_step_f32c2(const StepArgs& a, int K, int face_mode, int grid, 
 hipError_t launch_step_f64c2(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
 hipError_t launch_step_f64c1(const StepArgs& a, int K, int face_mode, int grid, hipStream_t s);
 hipError_t launch_persistent_f32c4(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
-                                   hipStream_t s);
+                                   const PersistentExtra& x, hipStream_t s);
 hipError_t launch_persistent_f32c2(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
-                                   hipStream_t s);
+                                   const PersistentExtra& x, hipStream_t s);
 hipError_t launch_persistent_f64c2(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
-                                   hipStream_t s);
+                                   const PersistentExtra& x, hipStream_t s);
 hipError_t launch_persistent_f64c1(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
-                                   hipStream_t s);
+                                   const PersistentExtra& x, hipStream_t s);
 int persistent_max_f32c4(int K, int face_mode);
 int persistent_max_f32c2(int K, int face_mode);
 int persistent_max_f64c2(int K, int face_mode);
@@ -61,18 +61,18 @@ hipError_t launch_step<double>(const StepArgs& a, int K, int C, int face_mode, i
 }
 template <>
 hipError_t launch_step_persistent<float>(const StepArgs& a, int K, int C, int face_mode, int phases, int grid, int* bar,
-                                         hipStream_t s)
+                                         const PersistentExtra& x, hipStream_t s)
 {
-    if (C == 4) return launch_persistent_f32c4(a, K, face_mode, phases, grid, bar, s);
-    if (C == 2) return launch_persistent_f32c2(a, K, face_mode, phases, grid, bar, s);
+    if (C == 4) return launch_persistent_f32c4(a, K, face_mode, phases, grid, bar, x, s);
+    if (C == 2) return launch_persistent_f32c2(a, K, face_mode, phases, grid, bar, x, s);
     return hipErrorInvalidValue;
 }
 template <>
 hipError_t launch_step_persistent<double>(const StepArgs& a, int K, int C, int face_mode, int phases, int grid,
-                                          int* bar, hipStream_t s)
+                                          int* bar, const PersistentExtra& x, hipStream_t s)
 {
-    if (C == 2) return launch_persistent_f64c2(a, K, face_mode, phases, grid, bar, s);
-    if (C == 1) return launch_persistent_f64c1(a, K, face_mode, phases, grid, bar, s);
+    if (C == 2) return launch_persistent_f64c2(a, K, face_mode, phases, grid, bar, x, s);
+    if (C == 1) return launch_persistent_f64c1(a, K, face_mode, phases, grid, bar, x, s);
     return hipErrorInvalidValue;
 }
 template <>
@@ -95,12 +95,13 @@ int persistent_max_blocks<double>(int K, int C, int face_mode)
 // grid = (levels, nmembers)
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table, int first, double* energy_base,
-                                                         int64_t energy_stride, int64_t energy_offset, int* health)
+                                                         int64_t energy_stride, int64_t energy_offset, int* health,
+                                                         int slot)
 {
     const int t = blockIdx.x;
     const int m = first + blockIdx.y;
     const MemberDev& M = table[m];
-    const double* p = M.epart + (size_t)t * M.epart_stride;
+    const double* p = M.epart + ((size_t)slot * kMaxTimeBlock + t) * M.epart_stride;
     // four independent chains so that the loads of a thread are in flight together
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     const int nw = M.waves;
@@ -135,16 +136,16 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table,
 
 template <typename T>
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
-                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s)
+                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s, int slot)
 {
     hipLaunchKernelGGL(k_energy_finalize, dim3(levels, nmembers), dim3(256), 0, s, table, first, energy_base,
-                       energy_stride, energy_offset, health);
+                       energy_stride, energy_offset, health, slot);
     return hipGetLastError();
 }
 template hipError_t launch_energy_finalize<float>(const MemberDev*, int, int, int, double*, int64_t, int64_t, int*,
-                                                  hipStream_t);
+                                                  hipStream_t, int);
 template hipError_t launch_energy_finalize<double>(const MemberDev*, int, int, int, double*, int64_t, int64_t, int*,
-                                                   hipStream_t);
+                                                   hipStream_t, int);
 
 // ------------------------------------------------------------------------------------------
 // Block reduction helpers (fixed order) for the generic two-stage reductions.
@@ -564,6 +565,13 @@ __global__ void k_fill_bytes(uint4* p, size_t n16, unsigned char* tail, size_t n
         p[k] = make_uint4(0u, 0u, 0u, 0u);
     if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
+__global__ void k_set_int(int* p, int v) { *p = v; }
+hipError_t launch_set_int(int* p, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_bytes(void* p, size_t bytes, hipStream_t s)
 {
     if (bytes == 0) return hipSuccess;

@@ -267,7 +267,7 @@ __device__ __forceinline__ void store_row_nt(T* __restrict__ p, const T (&in)[C]
 // MODE bit 0: per-step energy partials; bit 1: receiver traces; bit 2: non-temporal loads of
 // the state rows (FP32 launches whose working set exceeds the last-level cache).
 template <typename T, int K, int C, int FACE, int MODE>
-__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step)
+__device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int parity, int64_t ctx_step, int eslot = 0)
 {
     constexpr bool want_energy = (MODE & 1) != 0;
     constexpr bool want_trace = (MODE & 2) != 0;
@@ -568,7 +568,10 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
 #pragma unroll
         for (int t = 0; t < K; ++t) {
             const double sum = wave_sum(acc[t]);
-            if (lane == 0) M.epart[(size_t)t * M.epart_stride + wave] = sum;
+            // every lane stores the same sum (the butterfly leaves it in all lanes): no lane-0
+            // branch, which inside the persistent kernel's item loop could be moved out of the
+            // loop for lane 0 alone
+            M.epart[((size_t)eslot * kMaxTimeBlock + t) * M.epart_stride + wave] = sum;
         }
     }
 }
@@ -641,12 +644,11 @@ static hipError_t launch_step_c(const StepArgs& a, int K, int face_mode, int gri
 }
 
 // ------------------------------------------------------------------------------------------
-// Persistent batched variant: one cooperative launch runs `phases` time blocks of K steps
-// (plus a final block of tail_K steps) over all members, with a grid-wide barrier between
-// time blocks.  The barrier spin is bounded: on expiry it records an error flag and lets the
-// wave continue, so a launch always drains.
+// Persistent batched variant: one cooperative launch runs `phases` time blocks of K steps over
+// all members, with a grid-wide barrier between time blocks.  The barrier spin is bounded: on
+// expiry it records an error flag and lets the wave continue, so a launch always drains.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
+__device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen, int* err)
 {
     // The block's stores reach its L2 by the workgroup barrier; one agent-scope release by
     // the arriving thread then writes that L2 back for the other XCDs (the L2 write-back and
@@ -666,7 +668,9 @@ __device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
             while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1L << 26)) {
-                    __hip_atomic_fetch_or(&bar[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // the wait is bounded: record the timeout in the caller's error word (the host
+                    // reads it after the call) and carry on, so that the launch always drains
+                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
@@ -679,8 +683,33 @@ __device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen)
     __syncthreads();
 }
 
-template <typename T, int K, int C, int FACE>
-__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar)
+// Energy of one (member, level) of a finished time block, summed by one wave in a fixed order
+// (lane l takes the partials l, l + 64, ... in turn, then a butterfly whose two operands are the
+// same in both lanes of a pair, so every lane ends with the same sum): the in-kernel counterpart
+// of k_energy_finalize, with the same failure-detection bits.  Every lane stores that same
+// value: a store under `lane == 0` inside the caller's loop let the compiler move lane 0 out of
+// the loop on its own, leaving the other lanes of the wave looping.
+__device__ __forceinline__ void finalize_energy_wave(const MemberDev& M, int m, int t, int slot, int64_t row_off,
+                                                     const PersistentExtra& x, bool growth_ok)
+{
+    const int lane = threadIdx.x & 63;
+    const double* p = M.epart + ((size_t)slot * kMaxTimeBlock + t) * M.epart_stride;
+    double acc = 0.0;
+    for (int w = lane; w < M.waves; w += kWaveSize) acc += p[w];
+    const double E = wave_sum(acc) * M.escale;
+    x.energy_base[(int64_t)m * x.energy_stride + row_off + t] = E;
+    int bits = isfinite(E) ? 0 : 1;
+    if (growth_ok && fabs(E) > 10.0 * fabs(x.energy_base[(int64_t)m * x.energy_stride])) bits |= 2;
+    if (bits) atomicOr(x.health, bits);
+}
+
+// MODE 0: plain steps; MODE 1: with the per-step energy.  In energy mode the time blocks write
+// their per-wave partials into two alternating slots, and the partials of time block p - 1 are
+// summed at the start of time block p (one wave per (member, level), handed out before the
+// stencil items); the last block's partials are summed by the host's k_energy_finalize.
+template <typename T, int K, int C, int FACE, int MODE>
+__global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(StepArgs a, int phases, int* bar,
+                                                                                PersistentExtra x)
 {
     const int total_waves = a.total_blocks * kWavesPerBlock;  // work items of one time block
     // Workgroups land on the 8 XCDs round-robin (block b on XCD b mod 8).  Each XCD takes a
@@ -693,38 +722,54 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(
     const int lo = by_xcd ? (int)((int64_t)total_waves * xcd / 8) : 0;
     const int hi = by_xcd ? (int)((int64_t)total_waves * (xcd + 1) / 8) : total_waves;
     const int lane = threadIdx.x & 63;
-    int* const counters = bar + 16;
+    int* const counters = bar + 16;  // [phases][8] stencil items
+    const int nfin = (MODE & 1) ? a.nmembers * K : 0;
+    const int gwave = (int)blockIdx.x * kWavesPerBlock + wave_in_block();
+    const int nwaves = (int)gridDim.x * kWavesPerBlock;
     int gen = 0;
     int parity = a.parity;
     int64_t step = a.ctx_step;
     for (int p = 0; p < phases; ++p) {
+        if ((MODE & 1) && p > 0) {
+            // energies of time block p - 1 (its partials are complete: a grid barrier separates
+            // them), one (member, level) per wave of the grid in turn: a loop with a wave-uniform
+            // (scalar) trip count
+            const int64_t q = p - 1;
+            for (int k = gwave; k < nfin; k += nwaves) {
+                const int m = a.first + k / K;
+                finalize_energy_wave(a.table[m], m, k % K, (int)(q & 1), x.energy_offset + q * K, x,
+                                     x.energy_offset > 0 || q >= 2);
+            }
+        }
         for (;;) {
             int k = 0;
             if (lane == 0) k = __hip_atomic_fetch_add(&counters[8 * p + xcd], 1, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
-            const int item = lo + __builtin_amdgcn_readfirstlane(k);
+            // lane 0's ticket, read from lane 0 whatever the active lanes
+            const int item = lo + __builtin_amdgcn_readlane(k, 0);
             if (item >= hi) break;
             const int gb = item / kWavesPerBlock + a.block_offset;
             const int m = find_member(a.table, a.first, a.nmembers, gb);
             const MemberDev& M = a.table[m];
             const int wave = (gb - M.block_base) * kWavesPerBlock + (item % kWavesPerBlock);
-            if (wave < M.waves) sweep_item<T, K, C, FACE, 0>(M, wave, parity, step);
+            if (wave < M.waves) sweep_item<T, K, C, FACE, MODE>(M, wave, parity, step, p & 1);
         }
         parity ^= 1;
         step += K;
-        if (p + 1 < phases) grid_barrier(bar, gridDim.x, gen);
+        if (p + 1 < phases) grid_barrier(bar, gridDim.x, gen, x.err);
     }
 }
 
 template <typename T, int K, int C>
-static hipError_t launch_persistent_kc(const StepArgs& a, int face_mode, int phases, int grid, int* bar, hipStream_t s)
+static hipError_t launch_persistent_kc(const StepArgs& a, int face_mode, int phases, int grid, int* bar,
+                                       const PersistentExtra& x, hipStream_t s)
 {
-    void* args[] = {(void*)&a, (void*)&phases, (void*)&bar};
-    if (face_mode == 1)
-        return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, C, 1>, dim3(grid),
-                                          dim3(kWaveSize * kWavesPerBlock), args, 0, s);
-    return hipLaunchCooperativeKernel((const void*)k_step_persistent<T, K, C, 0>, dim3(grid),
-                                      dim3(kWaveSize * kWavesPerBlock), args, 0, s);
+    void* args[] = {(void*)&a, (void*)&phases, (void*)&bar, (void*)&x};
+    const dim3 g(grid), b(kWaveSize * kWavesPerBlock);
+    const bool e = a.want_energy != 0;
+    const void* f = face_mode == 1 ? (e ? (const void*)k_step_persistent<T, K, C, 1, 1> : (const void*)k_step_persistent<T, K, C, 1, 0>)
+                                   : (e ? (const void*)k_step_persistent<T, K, C, 0, 1> : (const void*)k_step_persistent<T, K, C, 0, 0>);
+    return hipLaunchCooperativeKernel(f, g, b, args, 0, s);
 }
 
 template <typename T, int K, int C>
@@ -732,8 +777,9 @@ static int persistent_blocks_kc(int face_mode)
 {
     int per_cu = 0;
     const int bs = kWaveSize * kWavesPerBlock;
-    hipError_t e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 1>, bs, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 0>, bs, 0);
+    // the energy variant holds more registers: size the grid for it, so both fit
+    hipError_t e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 1, 1>, bs, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 0, 1>, bs, 0);
     if (e != hipSuccess) return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -744,14 +790,14 @@ static int persistent_blocks_kc(int face_mode)
 // time blocks 1, 2, 4 and (when the configuration allows it) 8
 template <typename T, int C, int KMAX>
 static hipError_t launch_persistent_c(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
-                                      hipStream_t s)
+                                      const PersistentExtra& x, hipStream_t s)
 {
     switch (K) {
-    case 1: return launch_persistent_kc<T, 1, C>(a, face_mode, phases, grid, bar, s);
-    case 2: return launch_persistent_kc<T, 2, C>(a, face_mode, phases, grid, bar, s);
-    case 4: return launch_persistent_kc<T, 4, C>(a, face_mode, phases, grid, bar, s);
+    case 1: return launch_persistent_kc<T, 1, C>(a, face_mode, phases, grid, bar, x, s);
+    case 2: return launch_persistent_kc<T, 2, C>(a, face_mode, phases, grid, bar, x, s);
+    case 4: return launch_persistent_kc<T, 4, C>(a, face_mode, phases, grid, bar, x, s);
     case 8:
-        return KMAX >= 8 ? launch_persistent_kc<T, (KMAX >= 8 ? 8 : 1), C>(a, face_mode, phases, grid, bar, s)
+        return KMAX >= 8 ? launch_persistent_kc<T, (KMAX >= 8 ? 8 : 1), C>(a, face_mode, phases, grid, bar, x, s)
                          : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }

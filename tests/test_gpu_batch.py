@@ -134,3 +134,58 @@ def test_full_family_launch_configuration():
         rel = np.abs(u - ref).max() / np.abs(ref).max()
         _say("member", m, "fp32 rel", rel)
         assert rel <= 1e-5
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "f64"])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_persistent_with_energy_vs_oracle(dtype_name, graph):
+    """The persistent launch with the per-step energy summed inside it, plain and replayed from a
+    hipGraph, member by member against the oracle: states (FP64 max-abs 1e-12, FP32 1e-5
+    relative) and every energy (FP64 1e-12 relative, FP32 1e-5 relative); the state equals the
+    per-time-block launches bit for bit and the energies agree with theirs to rounding.  Two
+    calls of 1 + 150 + 52 steps: the start step, a call that spans the in-kernel energy sums,
+    and one with a tail; the graph is replayed for a second solve from step 0."""
+    fdw = _fdw()
+    dt = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
+    fam = _small_family(count=8, nsteps=203)
+    _say("persistent + energy vs oracle", dtype_name, "graph", graph)
+    a = fdw.family_solver(fam, dtype=dt)
+    Ea = a.step(203, energy=True).cpu().numpy()
+    sa = _states(a)
+    a.close()
+    b = fdw.family_solver(fam, dtype=dt)
+    b.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+    b.configure(fdw.FDW_CFG_USE_GRAPH, graph)
+    for rep in range(2 if graph else 1):
+        for m in range(len(fam)):
+            b.reset(m)
+        E = np.concatenate([b.step(k, energy=True).cpu().numpy() for k in (1, 150, 52)], axis=1)
+        sb = _states(b)
+        for m, case in enumerate(fam):
+            assert np.array_equal(sa[m][0], sb[m][0]) and np.array_equal(sa[m][1], sb[m][1]), (rep, m)
+            assert np.abs(E[m] - Ea[m]).max() <= (1e-13 if dt == fdw.FDW_F64 else 1e-6) * abs(Ea[m][0]), (rep, m)
+            ref = oracle.forward_case(case, want_energy=True)
+            if dt == fdw.FDW_F64:
+                assert np.abs(sb[m][0] - ref["u_cur"]).max() <= 1e-12
+                assert np.abs(E[m] - ref["energy"]).max() <= 1e-12 * ref["energy"][0]
+            else:
+                assert np.abs(sb[m][0] - ref["u_cur"]).max() <= 1e-5 * np.abs(ref["u_cur"]).max()
+                assert np.abs(E[m] - ref["energy"]).max() <= 1e-5 * ref["energy"][0]
+    b.close()
+
+
+def test_persistent_barrier_timeout_is_reported():
+    """The persistent launch's barrier error word is read back after the call: the host marks it
+    (test hook; no kernel waits on it) and the call returns FDW_ESYNC; the next call is clean."""
+    fdw = _fdw()
+    fam = _small_family(count=4, nsteps=60)
+    s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
+    s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+    s.step(1)
+    s.configure(fdw.FDW_CFG_TEST_BARRIER_FLAG, 1)
+    with pytest.raises(fdw.FdwError) as e:
+        s.step(16)
+    assert e.value.status == fdw.FDW_ESYNC
+    assert s.config(fdw.FDW_CFG_TEST_BARRIER_FLAG) == 0
+    s.step(16)
+    s.close()
