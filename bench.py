@@ -140,12 +140,15 @@ def copy_bench(torch, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / dt / 1e9
 
 
-def small_bench(fdw, torch, I, steps):
+def small_bench(fdw, torch, I, steps, persistent=False):
     """The 256^2 FP64 line workload (1000 steps + energy): cache-resident and launch-bound,
-    reported as microseconds per step with the launch sequence replayed from a graph."""
+    reported as microseconds per step with the launch sequence replayed from a graph (one
+    launch per time block, or one persistent launch with grid barriers)."""
     case = I.line_case(n=256, nsteps=1000)
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
     s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
+    if persistent:
+        s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
     h = torch.as_tensor(case.h1, device="cuda")
     e = torch.empty((1, case.nsteps), dtype=torch.float64, device="cuda")
 
@@ -218,18 +221,21 @@ def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
     return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par)
 
 
-def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False):
+def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, fp64_smallest=0):
     """The 32-member family, 2000 steps each: one launch per time block over all members
     (persistent=False) or one persistent cooperative launch per call (persistent=True), both
-    replayed from a hipGraph; optionally with the per-step energy of every member."""
+    replayed from a hipGraph; optionally with the per-step energy of every member, and with the
+    fp64_smallest smallest-eps members stored in FP64 (the rest FP32)."""
     fam = I.family()
-    s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
+    dts = [fdw.FDW_F32] * (len(fam) - fp64_smallest) + [fdw.FDW_F64] * fp64_smallest
+    s = fdw.family_solver(fam, dtype=dts)
     s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
     if persistent:
         s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
     nsteps = fam[0].nsteps
     updates = sum((c.nx - 2) * (c.ny - 2) * c.nsteps for c in fam)
-    bytes_alg = sum(c.nx * c.ny for c in fam) * 5 * 4 * nsteps / s.config(fdw.FDW_CFG_TIME_BLOCK)
+    bytes_alg = sum(c.nx * c.ny * (8 if d == fdw.FDW_F64 else 4) for c, d in zip(fam, dts)) * 5 * nsteps / \
+        s.config(fdw.FDW_CFG_TIME_BLOCK)
     del fam
     e = torch.empty((s.count, nsteps), dtype=torch.float64, device="cuda") if energy else None
 
@@ -650,6 +656,8 @@ def main():
         log(json.dumps(fame))
         famp = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup, persistent=True, energy=True)
         log(json.dumps(famp))
+        famx = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup, energy=True, fp64_smallest=4)
+        log(json.dumps(famx))
         out["batched"] = {"value": round(fam["ups"], 1), "unit": "grid-point updates/s", "members": 32,
                           "ms_per_step": round(fam["sec"] * 1e3, 2), "time_block": fam["K"],
                           "alg_GBs": round(fam["alg_GBs"], 1), "frac": round(fam["alg_GBs"] / HBM_PEAK_GBS, 4),
@@ -659,12 +667,16 @@ def main():
                           "persistent_energy_frac": round(famp["alg_GBs"] / HBM_PEAK_GBS, 4),
                           "persistent_energy_ms_per_step": round(famp["sec"] * 1e3, 2),
                           "energy_drift_max": famp["energy_drift"],
+                          "mixed_fp64_smallest4_energy_value": round(famx["ups"], 1),
+                          "mixed_fp64_smallest4_energy_ms_per_step": round(famx["sec"] * 1e3, 2),
                           "workload": "32 regularisations, eps log-spaced 0.1 .. 2dx, delta line / Heaviside jump, "
                                       "512^2-4096^2, 2000 steps, FP32; value: one launch per time block covering "
                                       "all members, replayed from a hipGraph; energy_value: the same with the "
                                       "per-step energy of every member; persistent_energy_value: one cooperative "
                                       "launch per call (grid barrier between time blocks, energies summed in the "
-                                      "launch), replayed from a hipGraph"}
+                                      "launch), replayed from a hipGraph; mixed_fp64_smallest4: the four smallest-eps "
+                                      "members (4096^2 .. 512^2) stored in FP64, the rest FP32, one launch sequence "
+                                      "per storage type, with energies"}
         torch.cuda.empty_cache()
         log("adjoint 2048^2 fp64 x 4000")
         adj = adjoint_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
@@ -686,7 +698,9 @@ def main():
         torch.cuda.empty_cache()
         log("small 256^2 fp64 line")
         sm = small_bench(fdw, torch, I, args.steps)
+        smp = small_bench(fdw, torch, I, args.steps, persistent=True)
         out["small"] = {"us_per_step": round(sm["us_per_step"], 3), "time_block": sm["K"],
+                        "persistent_us_per_step": round(smp["us_per_step"], 3),
                         "workload": "256x256 FP64 line singularity h = 1 + 2 phi_0.05(x), 1000 steps with per-step "
                                     "energy, launch sequence replayed from a hipGraph (cache-resident)"}
         log("largest 16384^2 fp32")

@@ -86,7 +86,8 @@ typedef struct {
 size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count);
 
 /* Create a context for `count` >= 1 members (count > 1 is a batched family: members may
- * differ in size, tau and coefficient but share the storage type).  Each member is one
+ * differ in size, tau, coefficient and storage type; a family that mixes FP32 and FP64
+ * members, e.g. FP64 for its smallest-eps members, runs one launch sequence per type).  Each member is one
  * regularised Cauchy problem: the Cauchy data u(0) = u0, u_t(0) = u1 of eq. (2.1) (Section 2)
  * on the grid with zero Dirichlet data of Section 3.3; a family holds several
  * regularisations h_eps of one singular depth (Section 2.1, Section 3.2).
@@ -199,7 +200,7 @@ int fdw_get_state(fdw_ctx* ctx, int32_t member, void* u, void* du, int64_t* n);
  * n >= 1 (at n = 0 the state is defined by the initial data). */
 int fdw_set_state(fdw_ctx* ctx, int32_t member, const void* u, const void* du, int64_t n);
 
-/* L2 distance of two members' current fields, sqrt(dx dy sum (u_a - u_b)^2) in double: the
+/* L2 distance of two members' current fields (of one storage type: FDW_ENOTSUP otherwise), sqrt(dx dy sum (u_a - u_b)^2) in double: the
  * norm ||u_eps1(t, .) - u_eps2(t, .)||_{L^2} of Section 3.2.1 (limiting behaviour as eps -> 0)
  * and of the consistency statement of Section 2.3 (Theorem 2.6), for regularisations on the
  * same grid.  Both
@@ -219,6 +220,8 @@ int64_t fdw_steps_taken(const fdw_ctx* ctx, int32_t member);
  *   FDW_CFG_SEGMENT_ROWS: rows per streaming work item, 8..4096 (0 = automatic);
  *   FDW_CFG_USE_GRAPH: 1 captures the launch sequence of a step_n call in a hipGraph and
  *     replays it for later calls with the same shape (0 = plain launches);
+ * On a family that mixes storage types a setting applies to both types and must be valid for
+ * both; fdw_get_config reports the FP32 members' value.
  *   FDW_CFG_BATCH_MODE: 0 = one launch per time block covering all members, 1 = one persistent
  *     cooperative launch per step_n call (up to 8192 steps per launch) with the energies summed
  *     in the launch; combined with FDW_CFG_USE_GRAPH the launch is replayed from a hipGraph.

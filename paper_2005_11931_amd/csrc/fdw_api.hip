@@ -104,6 +104,12 @@ struct fdw_ctx {
     int64_t ctx_step = 0;
     int64_t launches = 0;
     std::map<std::tuple<int64_t, int, const double*, int, int>, GraphEntry> graphs;
+    // A family whose members do not all share one storage type is held as one child context per
+    // type (member m of the family is member sub_idx[m] of child sub_of[m]); the parent itself
+    // holds no state and forwards every call.
+    bool mixed = false;
+    fdw_ctx* sub[2] = {nullptr, nullptr};
+    std::vector<int> sub_of, sub_idx;
 };
 
 namespace {
@@ -601,7 +607,7 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
             // all are in lock-step afterwards
             for (int i = 0; i < c->count; ++i) {
                 HostMember& hm = c->m[i];
-                double* e = energy_dev ? energy_dev + (int64_t)i * n : nullptr;
+                double* e = energy_dev ? energy_dev + (int64_t)c->tab[i].energy_row * n : nullptr;
                 if (hm.n == 0) {
                     int rc = do_start<T>(c, i, e);
                     if (rc) return rc;
@@ -664,6 +670,31 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
 
 }  // namespace
 
+// ---- families that mix storage types (one child context per type) --------------------------
+bool mixed_types(const fdw_problem* p, int count)
+{
+    for (int i = 1; i < count; ++i)
+        if (p[i].dtype != p[0].dtype) return true;
+    return false;
+}
+
+// the members of one storage type, in family order
+void members_of_type(const fdw_problem* p, int count, int dtype, std::vector<fdw_problem>* ps, std::vector<int>* idx)
+{
+    for (int i = 0; i < count; ++i)
+        if (p[i].dtype == dtype) {
+            ps->push_back(p[i]);
+            idx->push_back(i);
+        }
+}
+
+// a child's status, with its message, as the parent's
+int fwd(fdw_ctx* c, const fdw_ctx* child, int rc)
+{
+    if (rc) c->err = child->err;
+    return rc;
+}
+
 // =============================================================================================
 // C-ABI
 // =============================================================================================
@@ -690,6 +721,21 @@ const char* fdw_last_error(const fdw_ctx* c) { return c ? c->err.c_str() : "null
 size_t fdw_workspace_bytes(const fdw_problem* problems, int32_t count)
 {
     if (!problems || count < 1) return 0;
+    if (mixed_types(problems, count)) {
+        // one child context per storage type, each in its own (aligned) part of the workspace
+        size_t b = 0;
+        for (int t = FDW_F32; t <= FDW_F64; ++t) {
+            std::vector<fdw_problem> ps;
+            std::vector<int> idx;
+            members_of_type(problems, count, t, &ps, &idx);
+            const size_t bt = ps.empty() ? 0 : fdw_workspace_bytes(ps.data(), (int)ps.size());
+            if (!ps.empty() && bt == 0) return 0;
+            b += align_up(bt, kAlign);
+        }
+        for (int i = 0; i < count; ++i)
+            if (problems[i].dtype != FDW_F32 && problems[i].dtype != FDW_F64) return 0;
+        return b;
+    }
     size_t b = header_bytes(count);
     std::string why;
     for (int i = 0; i < count; ++i) {
@@ -708,9 +754,55 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
     if (!problems || count < 1 || !workspace || !u0 || !u1) return FDW_EINVAL;
     if (((uintptr_t)workspace) % kAlign) return FDW_EINVAL;
     std::string why;
+    if (mixed_types(problems, count)) {
+        const size_t need = fdw_workspace_bytes(problems, count);
+        if (need == 0) return FDW_EINVAL;
+        if (ws_bytes < need) return FDW_ENOMEM;
+        for (int i = 0; i < count; ++i)
+            if (!u0[i] || !u1[i]) return FDW_EINVAL;
+        fdw_ctx* c = new fdw_ctx();
+        c->mixed = true;
+        c->count = count;
+        c->dtype = -1;
+        c->stream = (hipStream_t)hip_stream;
+        c->sub_of.assign(count, 0);
+        c->sub_idx.assign(count, 0);
+        size_t off = 0;
+        for (int t = FDW_F32; t <= FDW_F64; ++t) {
+            std::vector<fdw_problem> ps;
+            std::vector<int> idx;
+            members_of_type(problems, count, t, &ps, &idx);
+            std::vector<const void*> a0, a1;
+            for (size_t j = 0; j < idx.size(); ++j) {
+                c->sub_of[idx[j]] = t;
+                c->sub_idx[idx[j]] = (int)j;
+                a0.push_back(u0[idx[j]]);
+                a1.push_back(u1[idx[j]]);
+            }
+            const size_t bt = fdw_workspace_bytes(ps.data(), (int)ps.size());
+            int rc = fdw_init(ps.data(), (int)ps.size(), (char*)workspace + off, bt, a0.data(), a1.data(), hip_stream,
+                              &c->sub[t]);
+            if (rc) {
+                fdw_destroy(c);
+                return rc;
+            }
+            off += align_up(bt, kAlign);
+            // energies go to the family's row of each member
+            fdw_ctx* ch = c->sub[t];
+            for (size_t j = 0; j < idx.size(); ++j) {
+                ch->tab[j].energy_row = idx[j];
+                rc = push_member(ch, (int)j);
+                if (rc) {
+                    fdw_destroy(c);
+                    return rc;
+                }
+            }
+        }
+        *out = c;
+        return FDW_OK;
+    }
     for (int i = 0; i < count; ++i) {
         if (!problem_ok(problems[i], &why, nullptr)) return FDW_EINVAL;
-        if (problems[i].dtype != problems[0].dtype) return FDW_EINVAL;
         if (!u0[i] || !u1[i]) return FDW_EINVAL;
     }
     const size_t need = fdw_workspace_bytes(problems, count);
@@ -771,6 +863,7 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
 
         MemberDev& md = c->tab[i];
         std::memset(&md, 0, sizeof(md));
+        md.energy_row = i;
         md.nx = hm.nx;
         md.ny = hm.ny;
         md.ld = hm.ld;
@@ -822,6 +915,10 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
 void fdw_destroy(fdw_ctx* c)
 {
     if (!c) return;
+    for (fdw_ctx*& ch : c->sub) {
+        fdw_destroy(ch);
+        ch = nullptr;
+    }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     for (auto& kv : c->graphs)
         if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
@@ -847,6 +944,7 @@ int fdw_set_coeff(fdw_ctx* c, int32_t m, const void* h1, const void* h2)
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed) return fwd(c, c->sub[c->sub_of[m]], fdw_set_coeff(c->sub[c->sub_of[m]], c->sub_idx[m], h1, h2));
     if (!h1) return fail(c, FDW_EINVAL, "h1 is NULL");
     HostMember& hm = c->m[m];
     const int face = h2 ? 1 : 0;
@@ -884,6 +982,15 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
 {
     if (!c) return FDW_EINVAL;
     if (n < 0) return fail(c, FDW_EINVAL, "n must be >= 0");
+    if (c->mixed) {
+        // one launch sequence per storage type, one after the other on the stream; each writes
+        // the energy rows of its own members
+        for (fdw_ctx* ch : c->sub) {
+            const int rc = fdw_step_n(ch, n, energy_dev);
+            if (rc) return fwd(c, ch, rc);
+        }
+        return FDW_OK;
+    }
     std::vector<int64_t> n_before;
     for (const HostMember& hm : c->m) n_before.push_back(hm.n);
     const bool check = energy_dev && c->check_energy && n > 0;
@@ -920,6 +1027,16 @@ int fdw_step_n(fdw_ctx* c, int64_t n, double* energy_dev)
 int fdw_energy(fdw_ctx* c, double* energy_host)
 {
     if (!c || !energy_host) return FDW_EINVAL;
+    if (c->mixed) {
+        std::vector<double> part[2];
+        for (int t = 0; t < 2; ++t) {
+            part[t].assign(c->sub[t]->count, 0.0);
+            const int rc = fdw_energy(c->sub[t], part[t].data());
+            if (rc) return fwd(c, c->sub[t], rc);
+        }
+        for (int i = 0; i < c->count; ++i) energy_host[i] = part[c->sub_of[i]][c->sub_idx[i]];
+        return FDW_OK;
+    }
     for (int i = 0; i < c->count; ++i)
         if (c->m[i].n < 1) return fail(c, FDW_ESTATE, "energy needs at least one step");
     for (int i = 0; i < c->count; ++i) {
@@ -940,6 +1057,8 @@ int fdw_record_traces(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, 
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed)
+        return fwd(c, c->sub[c->sub_of[m]], fdw_record_traces(c->sub[c->sub_of[m]], c->sub_idx[m], recv_ij, R, traces));
     HostMember& hm = c->m[m];
     if (R < 0 || R > kMaxReceivers) return fail(c, FDW_EINVAL, "R out of range");
     if (R == 0 || !traces) {
@@ -986,6 +1105,9 @@ int fdw_misfit(fdw_ctx* c, int32_t m, const void* traces, const double* d, int64
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed)
+        return fwd(c, c->sub[c->sub_of[m]],
+                   fdw_misfit(c->sub[c->sub_of[m]], c->sub_idx[m], traces, d, rows, R, J_dev, trace_grad));
     if (!traces || !d || !J_dev || rows < 0 || R < 0) return fail(c, FDW_EINVAL, "bad misfit arguments");
     const int64_t n = rows * (int64_t)R;
     HIPCHK(c, (c->dtype == FDW_F32) ? launch_misfit<float>(traces, d, n, J_dev, trace_grad, c->red, c->stream)
@@ -997,6 +1119,7 @@ int fdw_get_state(fdw_ctx* c, int32_t m, void* u, void* du, int64_t* n)
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed) return fwd(c, c->sub[c->sub_of[m]], fdw_get_state(c->sub[c->sub_of[m]], c->sub_idx[m], u, du, n));
     HostMember& hm = c->m[m];
     if (n) *n = hm.n;
     const void* su = (hm.n == 0) ? hm.u0 : hm.u[hm.cur];
@@ -1017,6 +1140,7 @@ int fdw_set_state(fdw_ctx* c, int32_t m, const void* u, const void* du, int64_t 
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed) return fwd(c, c->sub[c->sub_of[m]], fdw_set_state(c->sub[c->sub_of[m]], c->sub_idx[m], u, du, n));
     if (!u || !du || n < 1) return fail(c, FDW_EINVAL, "set_state needs u, du and n >= 1");
     HostMember& hm = c->m[m];
     if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
@@ -1037,6 +1161,11 @@ int fdw_member_distance(fdw_ctx* c, int32_t a, int32_t b, double* dist_host)
     if (rc) return rc;
     rc = check_member(c, b);
     if (rc) return rc;
+    if (c->mixed) {
+        if (c->sub_of[a] != c->sub_of[b]) return fail(c, FDW_ENOTSUP, "members of different storage types");
+        fdw_ctx* ch = c->sub[c->sub_of[a]];
+        return fwd(c, ch, fdw_member_distance(ch, c->sub_idx[a], c->sub_idx[b], dist_host));
+    }
     if (!dist_host) return fail(c, FDW_EINVAL, "dist_host is NULL");
     const HostMember& A = c->m[a];
     const HostMember& B = c->m[b];
@@ -1059,6 +1188,7 @@ int fdw_reset(fdw_ctx* c, int32_t m)
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed) return fwd(c, c->sub[c->sub_of[m]], fdw_reset(c->sub[c->sub_of[m]], c->sub_idx[m]));
     c->m[m].n = 0;
     c->m[m].cur = 0;
     if (c->rec.member == m) c->rec.member = -1;
@@ -1070,12 +1200,21 @@ int fdw_reset(fdw_ctx* c, int32_t m)
 int64_t fdw_steps_taken(const fdw_ctx* c, int32_t m)
 {
     if (!c || m < 0 || m >= c->count) return -1;
+    if (c->mixed) return fdw_steps_taken(c->sub[c->sub_of[m]], c->sub_idx[m]);
     return c->m[m].n;
 }
 
 int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
 {
     if (!c) return FDW_EINVAL;
+    if (c->mixed) {
+        // applied to both storage types (a value must be valid for both)
+        for (fdw_ctx* ch : c->sub) {
+            const int rc = fdw_configure(ch, key, v);
+            if (rc) return fwd(c, ch, rc);
+        }
+        return FDW_OK;
+    }
     switch (key) {
     case FDW_CFG_TIME_BLOCK:
         if (v < 0 || v > kMaxTimeBlock || (c->dtype == FDW_F64 && c->C == 2 && v > 4) || (c->C == 4 && v > 6))
@@ -1147,6 +1286,21 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
 int fdw_kernel_time(fdw_ctx* c, double* ms, int64_t* launches)
 {
     if (!c || !ms || !launches) return FDW_EINVAL;
+    if (c->mixed) {
+        double tot = 0.0;
+        int64_t nl = 0;
+        for (fdw_ctx* ch : c->sub) {
+            double t = 0.0;
+            int64_t k = 0;
+            const int rc = fdw_kernel_time(ch, &t, &k);
+            if (rc) return fwd(c, ch, rc);
+            tot += t;
+            nl += k;
+        }
+        *ms = tot;
+        *launches = nl;
+        return FDW_OK;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
     for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
@@ -1163,6 +1317,7 @@ int fdw_kernel_time(fdw_ctx* c, double* ms, int64_t* launches)
 int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
 {
     if (!c) return -1;
+    if (c->mixed) return fdw_get_config(c->sub[FDW_F32], key);  // the FP32 members' configuration
     switch (key) {
     case FDW_CFG_TIME_BLOCK: return choose_K(c);
     case FDW_CFG_SEGMENT_ROWS: return c->S_eff;
@@ -1403,6 +1558,7 @@ extern "C" {
 size_t fdw_adjoint_workspace_bytes(const fdw_ctx* c, int32_t m, int32_t ckpt_every)
 {
     if (!c || m < 0 || m >= c->count || ckpt_every < 1) return 0;
+    if (c->mixed) return fdw_adjoint_workspace_bytes(c->sub[c->sub_of[m]], c->sub_idx[m], ckpt_every);
     return adj_layout(c, c->m[m], ckpt_every).total;
 }
 
@@ -1410,6 +1566,9 @@ int fdw_record_checkpoints(fdw_ctx* c, int32_t m, int32_t ckpt_every, void* adj_
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed)
+        return fwd(c, c->sub[c->sub_of[m]],
+                   fdw_record_checkpoints(c->sub[c->sub_of[m]], c->sub_idx[m], ckpt_every, adj_ws, adj_ws_bytes));
     if (!adj_ws) {
         if (c->rec.member == m) c->rec.member = -1;
         return FDW_OK;
@@ -1431,6 +1590,10 @@ int fdw_adjoint(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, const 
 {
     int rc = check_member(c, m);
     if (rc) return rc;
+    if (c->mixed)
+        return fwd(c, c->sub[c->sub_of[m]],
+                   fdw_adjoint(c->sub[c->sub_of[m]], c->sub_idx[m], recv_ij, R, trace_grad, ckpt_every, adj_ws,
+                               adj_ws_bytes, grad_h1, grad_h2));
     HostMember& hm = c->m[m];
     if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
     if (R < 0 || R > kMaxReceivers) return fail(c, FDW_EINVAL, "R out of range");
@@ -1502,6 +1665,14 @@ void cache_store(const std::string& key, int K, int S, int C)
 extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
 {
     if (!c) return FDW_EINVAL;
+    if (c->mixed) {
+        // each storage type is tuned on its own; best_out reports the FP32 members' choice
+        for (int t = FDW_F64; t >= FDW_F32; --t) {
+            const int rc = fdw_autotune(c->sub[t], steps, t == FDW_F32 ? best_out : nullptr);
+            if (rc) return fwd(c, c->sub[t], rc);
+        }
+        return FDW_OK;
+    }
     for (const HostMember& hm : c->m) {
         if (!hm.coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff first");
         if (hm.n != 0) return fail(c, FDW_ESTATE, "autotune runs from step 0 (call fdw_reset first)");

@@ -36,6 +36,8 @@ struct MemberDev {
     int blocks;      // ceil(waves / kWavesPerBlock)
     int block_base;  // first block of this member in an all-member launch
     int cur0;        // buffer pair holding the state when the launch parity is 0
+    int energy_row;  // row of this member in the caller's [count][n] energy array (its index in the
+                     // family; differs from the index in this table when the family mixes storage types)
     int R;           // receivers (0: no trace recording)
     int64_t n_offset;    // member step = context step + n_offset
     int64_t trace_rows;  // N + 1
@@ -74,7 +76,7 @@ struct StepArgs {
 // Extra arguments of the persistent launch: where its energies go (as for
 // launch_energy_finalize) and its error words.
 struct PersistentExtra {
-    double* energy_base;    // energy of member m, step k of the call: energy_base[m * energy_stride + k]
+    double* energy_base;    // energy of member m, step k of the call: energy_base[row_m * energy_stride + k]
     int64_t energy_stride;
     int64_t energy_offset;  // step of the call the launch's first time block starts at
     int* health;            // failure detection, as for launch_energy_finalize
@@ -94,7 +96,7 @@ int persistent_max_blocks(int K, int C, int face_mode);
 
 template <typename T>
 // health (may be null): bit 0 set when an energy is non-finite, bit 1 when one exceeds 10x the
-// first energy of the call (energy_base[m * energy_stride])
+// first energy of the call (energy_base[row * energy_stride], row = MemberDev::energy_row)
 // slot: which of the two partial slots holds the levels (0 except after a persistent launch)
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
                                   int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s,

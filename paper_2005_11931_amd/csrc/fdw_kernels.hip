@@ -121,13 +121,13 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table,
     }
     if (threadIdx.x == 0) {
         const double E = red[0] * M.escale;
-        energy_base[(int64_t)m * energy_stride + energy_offset + t] = E;
+        energy_base[(int64_t)M.energy_row * energy_stride + energy_offset + t] = E;
         if (health) {
             // failure detection: a non-finite energy (bit 0), or growth beyond 10x the first
             // energy of the call (bit 1; that one was written by an earlier launch on the stream)
             if (!isfinite(E)) atomicOr(health, 1);
             if (energy_offset > 0) {
-                const double E0 = energy_base[(int64_t)m * energy_stride];
+                const double E0 = energy_base[(int64_t)M.energy_row * energy_stride];
                 if (fabs(E) > 10.0 * fabs(E0)) atomicOr(health, 2);
             }
         }

@@ -689,7 +689,7 @@ __device__ __forceinline__ void grid_barrier(int* bar, int nblocks, int& gen, in
 // of k_energy_finalize, with the same failure-detection bits.  Every lane stores that same
 // value: a store under `lane == 0` inside the caller's loop let the compiler move lane 0 out of
 // the loop on its own, leaving the other lanes of the wave looping.
-__device__ __forceinline__ void finalize_energy_wave(const MemberDev& M, int m, int t, int slot, int64_t row_off,
+__device__ __forceinline__ void finalize_energy_wave(const MemberDev& M, int t, int slot, int64_t row_off,
                                                      const PersistentExtra& x, bool growth_ok)
 {
     const int lane = threadIdx.x & 63;
@@ -697,9 +697,9 @@ __device__ __forceinline__ void finalize_energy_wave(const MemberDev& M, int m, 
     double acc = 0.0;
     for (int w = lane; w < M.waves; w += kWaveSize) acc += p[w];
     const double E = wave_sum(acc) * M.escale;
-    x.energy_base[(int64_t)m * x.energy_stride + row_off + t] = E;
+    x.energy_base[(int64_t)M.energy_row * x.energy_stride + row_off + t] = E;
     int bits = isfinite(E) ? 0 : 1;
-    if (growth_ok && fabs(E) > 10.0 * fabs(x.energy_base[(int64_t)m * x.energy_stride])) bits |= 2;
+    if (growth_ok && fabs(E) > 10.0 * fabs(x.energy_base[(int64_t)M.energy_row * x.energy_stride])) bits |= 2;
     if (bits) atomicOr(x.health, bits);
 }
 
@@ -737,7 +737,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step_persistent(
             const int64_t q = p - 1;
             for (int k = gwave; k < nfin; k += nwaves) {
                 const int m = a.first + k / K;
-                finalize_energy_wave(a.table[m], m, k % K, (int)(q & 1), x.energy_offset + q * K, x,
+                finalize_energy_wave(a.table[m], k % K, (int)(q & 1), x.energy_offset + q * K, x,
                                      x.energy_offset > 0 || q >= 2);
             }
         }

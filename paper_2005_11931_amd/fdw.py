@@ -142,12 +142,13 @@ class Solver:
         ws = _lib.fdw_workspace_bytes(arr, self.count)
         if ws == 0:
             raise FdwError(FDW_EINVAL, "invalid problem description")
-        self.dtype = problems[0].dtype
+        self.dtypes = [p.dtype for p in problems]
+        self.dtype = problems[0].dtype  # the first member's (a family may mix FP32 and FP64 members)
         self.tdtype = torch_dtype(self.dtype)
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
         self._keep = [t.contiguous() for t in list(u0) + list(u1)]
         for t, p in zip(u0, problems):
-            assert t.dtype == self.tdtype and tuple(t.shape) == (p.ny, p.nx), (t.dtype, t.shape)
+            assert t.dtype == torch_dtype(p.dtype) and tuple(t.shape) == (p.ny, p.nx), (t.dtype, t.shape)
         u0p = (_vp * self.count)(*[t.data_ptr() for t in self._keep[: self.count]])
         u1p = (_vp * self.count)(*[t.data_ptr() for t in self._keep[self.count:]])
         ctx = _vp()
@@ -209,7 +210,7 @@ class Solver:
         N = int(round(p.T / p.tau))
         rec = receivers.to(device=self.device, dtype=torch.int32).contiguous()
         R = rec.shape[0]
-        tr = torch.zeros((N + 1, R), dtype=self.tdtype, device=self.device)
+        tr = torch.zeros((N + 1, R), dtype=torch_dtype(p.dtype), device=self.device)
         self._traces[member] = (rec, tr)
         self._check(_lib.fdw_record_traces(self.ctx, member, _ptr(rec), R, _ptr(tr)))
         return tr
@@ -260,7 +261,7 @@ class Solver:
 
     def get_state(self, member: int = 0) -> Tuple[torch.Tensor, torch.Tensor, int]:
         p = self.problems[member]
-        u = torch.empty((p.ny, p.nx), dtype=self.tdtype, device=self.device)
+        u = torch.empty((p.ny, p.nx), dtype=torch_dtype(p.dtype), device=self.device)
         du = torch.empty_like(u)
         n = ctypes.c_int64()
         self._check(_lib.fdw_get_state(self.ctx, member, _ptr(u), _ptr(du), ctypes.byref(n)))
@@ -331,12 +332,15 @@ def solver_for_case(case, dtype: int = FDW_F64, device: str = "cuda:0", flags: i
     return s
 
 
-def family_solver(cases, dtype: int = FDW_F32, device: str = "cuda:0", flags: int = 0) -> Solver:
-    td = torch_dtype(dtype)
-    u0 = [torch.as_tensor(c.u0, dtype=td, device=device) for c in cases]
-    u1 = [torch.as_tensor(c.u1, dtype=td, device=device) for c in cases]
-    s = Solver([problem_from_case(c, dtype, flags) for c in cases], u0, u1, device=device)
-    for m, c in enumerate(cases):
+def family_solver(cases, dtype=FDW_F32, device: str = "cuda:0", flags: int = 0) -> Solver:
+    """A batched Solver over `cases`; dtype is one storage type for all members, or a list with
+    one per member (a family may hold FP64 members among FP32 ones)."""
+    dts = list(dtype) if isinstance(dtype, (list, tuple)) else [dtype] * len(cases)
+    u0 = [torch.as_tensor(c.u0, dtype=torch_dtype(d), device=device) for c, d in zip(cases, dts)]
+    u1 = [torch.as_tensor(c.u1, dtype=torch_dtype(d), device=device) for c, d in zip(cases, dts)]
+    s = Solver([problem_from_case(c, d, flags) for c, d in zip(cases, dts)], u0, u1, device=device)
+    for m, (c, d) in enumerate(zip(cases, dts)):
+        td = torch_dtype(d)
         s.set_coeff(torch.as_tensor(c.h1, dtype=td, device=device),
                     None if c.h2 is None else torch.as_tensor(c.h2, dtype=td, device=device), member=m)
     return s

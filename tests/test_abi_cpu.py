@@ -61,8 +61,13 @@ def test_host_validation(lib):
         fdw.fdw_problem(64, 48, -1, 1, -1, 1, 1e-3, 0.1, 7, 0),   # bad dtype
     ):
         assert ws(ctypes.byref(bad), 1) == 0
-    mixed = (fdw.fdw_problem * 2)(fdw.problem(64, 48, 1e-3, 10, fdw.FDW_F32), fdw.problem(64, 48, 1e-3, 10, fdw.FDW_F64))
-    assert ws(mixed, 2) == 0
+    # a family mixing storage types holds one child context per type: the sum of their workspaces
+    p32, p64 = fdw.problem(64, 48, 1e-3, 10, fdw.FDW_F32), fdw.problem(64, 48, 1e-3, 10, fdw.FDW_F64)
+    mixed = (fdw.fdw_problem * 2)(p32, p64)
+    align = lambda b: (b + 255) // 256 * 256
+    assert ws(mixed, 2) == align(ws(ctypes.byref(p32), 1)) + align(ws(ctypes.byref(p64), 1))
+    bad_mixed = (fdw.fdw_problem * 2)(p32, fdw.fdw_problem(64, 48, -1, 1, -1, 1, 1e-3, 0.01, 7, 0))
+    assert ws(bad_mixed, 2) == 0
     # init rejects NULL arguments before touching the device
     out = ctypes.c_void_p()
     lib.fdw_init.restype = ctypes.c_int

@@ -189,3 +189,52 @@ def test_persistent_barrier_timeout_is_reported():
     assert s.config(fdw.FDW_CFG_TEST_BARRIER_FLAG) == 0
     s.step(16)
     s.close()
+
+
+@pytest.mark.parametrize("batch_mode", [0, 1])
+def test_mixed_storage_family_vs_oracle(batch_mode):
+    """A family whose two smallest-eps members are stored in FP64 and the others in FP32 (one
+    launch sequence per storage type), with energies: every member against the oracle at its
+    own storage type's bar, the FP64 members equal to their single-member FP64 solves bit for
+    bit, energies in the family's row of each member, per-member state, traces and adjoint
+    routed to the right type, and the FP32-vs-FP64 distance refused."""
+    import torch
+
+    fdw = _fdw()
+    fam = _small_family(count=6, nsteps=120)
+    dts = [fdw.FDW_F32] * 4 + [fdw.FDW_F64] * 2
+    _say("mixed family, batch mode", batch_mode)
+    s = fdw.family_solver(fam, dtype=dts)
+    s.configure(fdw.FDW_CFG_BATCH_MODE, batch_mode)
+    E = s.step(120, energy=True).cpu().numpy()
+    st = _states(s)
+    for m, case in enumerate(fam):
+        ref = oracle.forward_case(case, want_energy=True)
+        if dts[m] == fdw.FDW_F64:
+            assert st[m][0].dtype == np.float64
+            u1, du1, e1 = _single(case, fdw.FDW_F64, 120, energy=True)
+            assert np.array_equal(st[m][0], u1) and np.array_equal(st[m][1], du1), m
+            assert np.abs(st[m][0] - ref["u_cur"]).max() <= 1e-12
+            assert np.abs(E[m] - ref["energy"]).max() <= 1e-12 * ref["energy"][0]
+        else:
+            assert st[m][0].dtype == np.float32
+            assert np.abs(st[m][0] - ref["u_cur"]).max() <= 1e-5 * np.abs(ref["u_cur"]).max()
+            assert np.abs(E[m] - ref["energy"]).max() <= 1e-5 * ref["energy"][0]
+    hosts = s.energy()
+    assert all(abs(hosts[m] - E[m][-1]) <= 1e-6 * abs(E[m][-1]) for m in range(len(fam)))
+    assert [s.steps_taken(m) for m in range(len(fam))] == [120] * len(fam)
+    with pytest.raises(fdw.FdwError) as e:
+        s.distance(0, 5)
+    assert e.value.status == fdw.FDW_ENOTSUP
+    # adjoint of an FP64 member of the mixed family against the oracle
+    case = fam[5]
+    # receivers at and beside the largest initial displacement (where the traces carry signal)
+    jm, im = np.unravel_index(np.argmax(np.abs(case.u0)), case.u0.shape)
+    rec = np.array([[im, jm], [im + 3, jm], [im, jm - 4]], dtype=np.int32)
+    N = case.nsteps
+    tg = np.random.default_rng(5).normal(size=(N + 1, 3))
+    g = s.adjoint(torch.as_tensor(rec), torch.as_tensor(tg), ckpt_every=16, member=5).cpu().numpy()
+    gref = oracle.adjoint(case.nx, case.ny, case.dx, case.dy, case.tau, case.h1, None, case.u0, case.u1, N, rec, tg,
+                          ckpt_every=16)
+    assert np.linalg.norm(g - gref) <= 1e-9 * np.linalg.norm(gref)
+    s.close()
