@@ -103,7 +103,7 @@ struct fdw_ctx {
     int S_eff = 0;
     int64_t ctx_step = 0;
     int64_t launches = 0;
-    std::map<std::tuple<int64_t, int, const double*, int, int>, GraphEntry> graphs;
+    std::map<std::tuple<int64_t, int, const double*, int, int, uint64_t>, GraphEntry> graphs;
     // A family whose members do not all share one storage type is held as one child context per
     // type (member m of the family is member sub_idx[m] of child sub_of[m]); the parent itself
     // holds no state and forwards every call.
@@ -639,8 +639,14 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
     if (c->use_graph && !any_trace(c) && !recording) {
         // The launch sequence of the main loop depends only on (steps, K, energy pointer and
         // offset, launch parity, batch mode); capture it once and replay it.
+        // The captured sequence rewrites the member table with the pair index each member's
+        // state sits in (cur0); with up to 64 members these are part of the key, so a graph is
+        // replayed only where they match and returning a member to step 0 need not drop graphs.
+        uint64_t pairs = 0;
+        if (c->count <= 64)
+            for (int i = 0; i < c->count; ++i) pairs |= (uint64_t)(c->tab[i].cur0 & 1) << i;
         const auto key = std::make_tuple(left, choose_K(c) + 16 * (int)persistent, (const double*)energy_dev,
-                                         (int)(c->launches & 1), (int)done);
+                                         (int)(c->launches & 1), (int)done, pairs);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1193,7 +1199,8 @@ int fdw_reset(fdw_ctx* c, int32_t m)
     c->m[m].cur = 0;
     if (c->rec.member == m) c->rec.member = -1;
     sync_member_dev(c, m);
-    invalidate_graphs(c);
+    // graphs stay valid: their key holds every member's pair index (families of up to 64)
+    if (c->count > 64) invalidate_graphs(c);
     return push_member(c, m);
 }
 
