@@ -181,6 +181,10 @@ def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
     h = torch.as_tensor(case.h1, dtype=torch.float32, device="cuda")
     updates = (n - 2) * (n - 2) * nsteps
+    # the temporal block depth (with lane columns and rows per item) chosen by the autotuner
+    t0 = time.perf_counter()
+    tuned = s.autotune()
+    tune_s = time.perf_counter() - t0
 
     def one():
         s.set_coeff(h)
@@ -218,10 +222,10 @@ def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
         del h
     torch.cuda.empty_cache()
     crop = adjoint_crop_bench(fdw, torch, I, case, max(1, steps), warmup, parity=parity)
-    return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par)
+    return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par, tuned=tuned, tune_s=tune_s)
 
 
-def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, fp64_smallest=0):
+def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, fp64_smallest=0, tune=False):
     """The 32-member family, 2000 steps each: one launch per time block over all members
     (persistent=False) or one persistent cooperative launch per call (persistent=True), both
     replayed from a hipGraph; optionally with the per-step energy of every member, and with the
@@ -232,6 +236,7 @@ def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, f
     s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
     if persistent:
         s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
+    tuned = s.autotune() if tune else None
     nsteps = fam[0].nsteps
     updates = sum((c.nx - 2) * (c.ny - 2) * c.nsteps for c in fam)
     bytes_alg = sum(c.nx * c.ny * (8 if d == fdw.FDW_F64 else 4) for c, d in zip(fam, dts)) * 5 * nsteps / \
@@ -259,7 +264,7 @@ def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, f
         drift = float(max(abs(E[m] - E[m][0]).max() / E[m][0] for m in range(E.shape[0])))
     s.close()
     return dict(sec=dt, updates=updates, ups=updates / dt, members=32, K=K, alg_GBs=bytes_alg / dt / 1e9,
-                energy_drift=drift)
+                energy_drift=drift, tuned=tuned)
 
 
 def adjoint_bench(fdw, torch, I, steps, warmup):
@@ -295,7 +300,7 @@ def adjoint_crop_bench(fdw, torch, I, full, steps, warmup, parity=True):
     rec = torch.as_tensor(case.receivers)
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
     tg = torch.as_tensor(np.random.default_rng(5004).normal(size=(N + 1, rec.shape[0])), device="cuda")
-    out = _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup)
+    out = _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup, tune=True)
     s.close()
     if parity:
         g32 = out.pop("grad")
@@ -308,10 +313,19 @@ def adjoint_crop_bench(fdw, torch, I, full, steps, warmup, parity=True):
     return out
 
 
-def _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup):
+def _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup, tune=False):
     """Forward solve, adjoint with its own replay, forward solve recording traces and
-    checkpoints (every 64 steps), adjoint from those checkpoints."""
+    checkpoints (every 64 steps), adjoint from those checkpoints.  tune: first autotune the
+    reverse sweep on a recorded forward run (not timed)."""
     N = case.nsteps
+    tuned = None
+    if tune:
+        s.reset()
+        s.record_checkpoints(64)
+        s.step(N)
+        tuned = s.autotune_adjoint(rec, tg, ckpt_every=64)
+        s.record_checkpoints(None)
+        s.reset()
     nb = fdw.lib().fdw_adjoint_workspace_bytes(s.ctx, 0, 64)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     g = torch.empty((case.ny, case.nx), dtype=torch.float64, device="cuda")
@@ -356,7 +370,7 @@ def _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup):
     tar = timed(adj_rec)
     return dict(forward_s=tf, adjoint_s=ta, ratio=ta / tf, forward_recording_s=tfr, adjoint_recorded_s=tar,
                 ratio_recorded=tar / tf, gradient_ratio=(tfr + tar) / tf, n=case.nx, nsteps=N,
-                grad_max=float(g.abs().max()), grad=g.cpu().numpy())
+                grad_max=float(g.abs().max()), grad=g.cpu().numpy(), adj_tuned=tuned)
 
 
 def cpu_baseline(I, budget_s=15.0):
@@ -650,7 +664,7 @@ def main():
             "frac": round(a64 / HBM_PEAK_GBS, 4), "energy_drift": f64["drift"]}
         torch.cuda.empty_cache()
         log("batched family")
-        fam = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup)
+        fam = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup, tune=True)
         log(json.dumps(fam))
         fame = family_bench(fdw, torch, I, max(1, args.steps - 1), args.warmup, energy=True)
         log(json.dumps(fame))
@@ -660,6 +674,7 @@ def main():
         log(json.dumps(famx))
         out["batched"] = {"value": round(fam["ups"], 1), "unit": "grid-point updates/s", "members": 32,
                           "ms_per_step": round(fam["sec"] * 1e3, 2), "time_block": fam["K"],
+                          "autotuned_time_block_segment_rows_lane_columns": fam["tuned"],
                           "alg_GBs": round(fam["alg_GBs"], 1), "frac": round(fam["alg_GBs"] / HBM_PEAK_GBS, 4),
                           "energy_value": round(fame["ups"], 1),
                           "energy_frac": round(fame["alg_GBs"] / HBM_PEAK_GBS, 4),
@@ -710,8 +725,10 @@ def main():
         out["parity"]["bathymetry16384"] = lg["parity"]
         out["largest"] = {"value": round(lg["ups"], 1), "unit": "grid-point updates/s",
                           "ms_per_step": round(lg["sec"] * 1e3, 2), "time_block": lg["K"],
+                          "autotuned_time_block_segment_rows_lane_columns": lg["tuned"],
+                          "autotune_s": round(lg["tune_s"], 2),
                           "workload": "16384x16384 FP32 smooth random bathymetry 0.2-1 + delta ridge eps = 2 dx, "
-                                      "10000 steps, no energy",
+                                      "10000 steps, no energy, launch configuration from the autotuner",
                           "adjoint_crop": {"forward_ms": round(cr["forward_s"] * 1e3, 2),
                                            "adjoint_ms": round(cr["adjoint_s"] * 1e3, 2),
                                            "ratio": round(cr["ratio"], 3),
@@ -719,6 +736,7 @@ def main():
                                            "adjoint_recorded_ms": round(cr["adjoint_recorded_s"] * 1e3, 2),
                                            "ratio_recorded": round(cr["ratio_recorded"], 3),
                                            "gradient_ratio": round(cr["gradient_ratio"], 3),
+                                           "adj_autotuned_time_block_segment_rows_lane_columns": cr.get("adj_tuned"),
                                            "fp32_grad_vs_fp64_gpu": cr.get("fp32_grad_vs_fp64_gpu"),
                                            "fp32_grad_vs_fp64_gpu_l2": cr.get("fp32_grad_vs_fp64_gpu_l2"),
                                            "workload": "central 4096x4096 crop of the same case (zero Dirichlet "

@@ -262,10 +262,22 @@ int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
  * step 0 (FDW_ESTATE otherwise) and is returned to step 0 (a checkpoint recording stops).
  * The choice is cached in the
  * file named by the FDW_AUTOTUNE_CACHE environment variable (if set) under a key of
- * (device arch, storage type, member sizes and layouts).  steps: time steps per candidate
+ * (device arch, storage type, member sizes and layouts, launch mode).  The candidates run in
+ * the context's own launch mode (FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE; the persistent launch
+ * only takes time blocks 1, 2, 4, 8).  steps: time steps per candidate
  * run (0 = automatic).  best_out (host, may be NULL) receives
  * {time_block, segment_rows, lane_columns}. */
 int fdw_autotune(fdw_ctx* ctx, int32_t steps, int64_t* best_out);
+
+/* Autotune the reverse sweep of member m (no passage: tuning): times fdw_adjoint with the given
+ * arguments (as for fdw_adjoint; the gradient goes to grad_scratch, device double [ny][nx], and
+ * the forward state is left unchanged) for each candidate (reverse time block, columns per lane,
+ * rows per work item) and applies the fastest.  With checkpoints recorded by the forward run in
+ * adj_ws the candidates time the reverse sweep alone.  Cached like fdw_autotune.  best_out (host,
+ * may be NULL) receives {adj_time_block, adj_segment_rows (0 = automatic), adj_lane_columns}. */
+int fdw_autotune_adjoint(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, int32_t R, const double* trace_grad,
+                         int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes, double* grad_scratch,
+                         int64_t* best_out);
 
 /* Instrumentation (no passage: measurement) (FDW_CFG_TIMING = 1, not under graph replay):
  * synchronise the stream and

@@ -1633,6 +1633,8 @@ std::string tune_key(const fdw_ctx* c)
     std::ostringstream os;
     os << arch << " " << (c->dtype == FDW_F32 ? "f32" : "f64") << " " << c->count;
     for (const HostMember& hm : c->m) os << " " << hm.nx << "x" << hm.ny << (hm.face ? "f" : "n");
+    // the launch mode the candidates were timed in
+    os << " g" << c->use_graph << "b" << c->batch_mode;
     return os.str();
 }
 
@@ -1706,9 +1708,10 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
             for (int K = 1; K <= 8; ++K) CK.push_back({1, K});
         }
         const int Ss[] = {8, 16, 32, 64, 128};
-        const int saveK = c->K_cfg, saveS = c->S_cfg, saveG = c->use_graph, saveB = c->batch_mode, saveC = c->C;
-        c->use_graph = 0;
-        c->batch_mode = 0;
+        // candidates run in the context's own launch mode (graph replay, persistent launch), so
+        // the choice is the best for the way the caller steps; the energy check is off meanwhile
+        const int saveCheck = c->check_energy;
+        c->check_energy = 0;
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
@@ -1718,10 +1721,13 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
             for (int S : Ss) {
                 if (S > 2 * maxny && S != 32) continue;
                 const int Kc = ck.second;
+                // the persistent launch runs time blocks of 1, 2, 4 or 8 only
+                if (c->batch_mode == 1 && (Kc & (Kc - 1)) != 0) continue;
                 c->C = ck.first;
                 c->K_cfg = Kc;
                 c->S_cfg = S;
                 c->S_eff = S;
+                invalidate_graphs(c);  // a graph holds the decomposition it was captured with
                 int rc = layout_for_K(c, Kc, S);
                 if (rc) return rc;
                 float med = 0.f;
@@ -1758,11 +1764,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
-        c->use_graph = saveG;
-        c->batch_mode = saveB;
-        (void)saveK;
-        (void)saveS;
-        (void)saveC;
+        c->check_energy = saveCheck;
         bestC_out = bestC;
         cache_store(key, bestK, bestS, bestC);
     }
@@ -1782,6 +1784,95 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         best_out[0] = bestK;
         best_out[1] = bestS;
         best_out[2] = c->C;
+    }
+    return FDW_OK;
+}
+
+// =============================================================================================
+// Autotuner of the reverse sweep
+// =============================================================================================
+extern "C" int fdw_autotune_adjoint(fdw_ctx* c, int32_t m, const int32_t* recv_ij, int32_t R, const double* trace_grad,
+                                    int32_t ckpt_every, void* adj_ws, size_t adj_ws_bytes, double* grad_scratch,
+                                    int64_t* best_out)
+{
+    int rc = check_member(c, m);
+    if (rc) return rc;
+    if (c->mixed) {
+        fdw_ctx* ch = c->sub[c->sub_of[m]];
+        return fwd(c, ch, fdw_autotune_adjoint(ch, c->sub_idx[m], recv_ij, R, trace_grad, ckpt_every, adj_ws,
+                                               adj_ws_bytes, grad_scratch, best_out));
+    }
+    if (!grad_scratch) return fail(c, FDW_EINVAL, "grad_scratch is NULL");
+    const HostMember& hm = c->m[m];
+    std::ostringstream key;
+    key << tune_key(c) << " adj m" << m << " c" << ckpt_every << " R" << R;
+    int bestK = c->adjK, bestC = c->adjC, bestS = c->adjS_cfg;
+    int cK = 0, cS = 0, cC = 0;
+    if (cache_lookup(key.str(), &cK, &cS, &cC)) {
+        bestK = cK;
+        bestS = cS;
+        bestC = cC;
+    } else {
+        // (columns per lane, reverse time block) pairs the kernels support, x rows per item (0: automatic)
+        std::vector<std::pair<int, int>> CK;
+        if (c->dtype == FDW_F64) {
+            for (int K = 2; K <= 6; ++K) CK.push_back({1, K});
+            for (int K = 2; K <= 4; ++K) CK.push_back({2, K});
+        } else {
+            for (int K = 2; K <= 6; ++K) CK.push_back({2, K});
+            for (int K = 2; K <= 4; ++K) CK.push_back({4, K});
+        }
+        const int Ss[] = {0, 16, 32, 64};
+        const int saveK = c->adjK, saveC = c->adjC, saveS = c->adjS_cfg;
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        float best = 1e30f;
+        for (const auto& ck : CK) {
+            for (int S : Ss) {
+                if (S > 0 && (S < 4 * ck.second || S > hm.ny)) continue;
+                c->adjC = ck.first;
+                c->adjK = ck.second;
+                c->adjS_cfg = S;
+                std::vector<float> ts;
+                for (int rep = 0; rep < 2; ++rep) {
+                    HIPCHK(c, hipEventRecord(e0, c->stream));
+                    rc = fdw_adjoint(c, m, recv_ij, R, trace_grad, ckpt_every, adj_ws, adj_ws_bytes, grad_scratch,
+                                     nullptr);
+                    if (rc) {
+                        c->adjK = saveK;
+                        c->adjC = saveC;
+                        c->adjS_cfg = saveS;
+                        hipEventDestroy(e0);
+                        hipEventDestroy(e1);
+                        return rc;
+                    }
+                    HIPCHK(c, hipEventRecord(e1, c->stream));
+                    HIPCHK(c, hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                    ts.push_back(ms);
+                }
+                const float t = std::min(ts[0], ts[1]);
+                if (t < best) {
+                    best = t;
+                    bestK = ck.second;
+                    bestC = ck.first;
+                    bestS = S;
+                }
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        cache_store(key.str(), bestK, bestS, bestC);
+    }
+    c->adjK = bestK;
+    c->adjC = bestC;
+    c->adjS_cfg = bestS;
+    if (best_out) {
+        best_out[0] = bestK;
+        best_out[1] = bestS;
+        best_out[2] = bestC;
     }
     return FDW_OK;
 }

@@ -37,7 +37,7 @@ EXPORTED = [
     "fdw_misfit", "fdw_adjoint_workspace_bytes", "fdw_record_checkpoints", "fdw_adjoint", "fdw_get_state", "fdw_set_state", "fdw_reset",
     "fdw_member_distance",
     "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_kernel_time", "fdw_last_error",
-    "fdw_status_string", "fdw_destroy", "fdw_misfit_noalloc", "fdw_noalloc_last_error",
+    "fdw_status_string", "fdw_destroy", "fdw_misfit_noalloc", "fdw_noalloc_last_error", "fdw_autotune_adjoint",
 ]
 
 
@@ -78,6 +78,9 @@ _lib.fdw_configure.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
 _lib.fdw_get_config.argtypes = [_vp, ctypes.c_int32]
 _lib.fdw_get_config.restype = ctypes.c_int64
 _lib.fdw_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+_lib.fdw_autotune_adjoint.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp,
+                                      ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int64)]
+_lib.fdw_autotune_adjoint.restype = ctypes.c_int
 _lib.fdw_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.fdw_kernel_time.restype = ctypes.c_int
 _lib.fdw_last_error.argtypes = [_vp]
@@ -301,6 +304,23 @@ class Solver:
         """Returns (time_block, segment_rows, lane_columns)."""
         out = (ctypes.c_int64 * 3)()
         self._check(_lib.fdw_autotune(self.ctx, int(steps), out))
+        return int(out[0]), int(out[1]), int(out[2])
+
+    def autotune_adjoint(self, receivers: torch.Tensor, trace_grad: torch.Tensor, ckpt_every: int = 64,
+                         member: int = 0) -> Tuple[int, int, int]:
+        """Tune the reverse sweep on this gradient problem (uses the recorded checkpoints when the
+        forward run stored them).  Returns (adj_time_block, adj_segment_rows, adj_lane_columns)."""
+        p = self.problems[member]
+        rec = receivers.to(device=self.device, dtype=torch.int32).contiguous()
+        tg = trace_grad.to(device=self.device, dtype=torch.float64).contiguous()
+        if self._ckpt is not None and self._ckpt[0] == member and self._ckpt[1] == ckpt_every:
+            ws = self._ckpt[2]
+        else:
+            ws = self._adjoint_workspace(member, ckpt_every)
+        g = torch.empty((p.ny, p.nx), dtype=torch.float64, device=self.device)
+        out = (ctypes.c_int64 * 3)()
+        self._check(_lib.fdw_autotune_adjoint(self.ctx, member, _ptr(rec), rec.shape[0], _ptr(tg), ckpt_every,
+                                              _ptr(ws), ws.numel(), _ptr(g), out))
         return int(out[0]), int(out[1]), int(out[2])
 
 

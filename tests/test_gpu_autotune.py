@@ -69,3 +69,73 @@ def test_autotune_choice_cache_and_bitwise_results(tmp_path, dtype_name):
         s3.close()
     finally:
         del os.environ["FDW_AUTOTUNE_CACHE"]
+
+
+@pytest.mark.parametrize("batch_mode", [0, 1])
+def test_autotune_in_graph_and_persistent_modes(tmp_path, batch_mode):
+    """Tuning under the context's own launch mode (hipGraph replay, and the persistent launch,
+    which takes time blocks 1, 2, 4, 8 only): the choice is cached under a key that names the
+    mode, and the tuned solve equals the default one bit for bit."""
+    from paper_2005_11931_amd import fdw
+
+    cases = _cases()
+    cache = tmp_path / "tune.txt"
+    os.environ["FDW_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        print("autotune graph, batch mode", batch_mode, flush=True)
+        s = fdw.family_solver(cases, dtype=fdw.FDW_F32)
+        s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
+        s.configure(fdw.FDW_CFG_BATCH_MODE, batch_mode)
+        K, S, C = s.autotune(steps=32)
+        if batch_mode == 1:
+            assert K in (1, 2, 4, 8)
+        assert s.config(fdw.FDW_CFG_USE_GRAPH) == 1 and s.config(fdw.FDW_CFG_BATCH_MODE) == batch_mode
+        assert f" g1b{batch_mode}|" in cache.read_text()
+        s.step(150)
+        tuned = [s.get_state(m)[0].cpu().numpy() for m in range(len(cases))]
+        s.close()
+        s3 = fdw.family_solver(cases, dtype=fdw.FDW_F32)
+        s3.step(150)
+        for m in range(len(cases)):
+            assert np.array_equal(tuned[m], s3.get_state(m)[0].cpu().numpy()), m
+        s3.close()
+    finally:
+        del os.environ["FDW_AUTOTUNE_CACHE"]
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_autotune_adjoint(tmp_path, dtype_name):
+    """Tuning the reverse sweep (time block, lane columns, rows per item) on a recorded forward
+    run: a supported choice is applied and cached, and the gradient it gives agrees with the
+    default configuration's (the time block groups the FP64 gradient sums differently, so to
+    rounding: 1e-12 relative in FP64)."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+
+    dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
+    case, _ = I.adjoint_case(n=384, nsteps=300, nrecv=16)
+    rec = torch.as_tensor(case.receivers)
+    tg = torch.as_tensor(np.random.default_rng(9).normal(size=(case.nsteps + 1, 16)))
+    cache = tmp_path / "tune.txt"
+    os.environ["FDW_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        print("autotune adjoint", dtype_name, flush=True)
+        s0 = fdw.solver_for_case(case, dtype=dt)
+        g0 = s0.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+        s0.close()
+        s = fdw.solver_for_case(case, dtype=dt)
+        s.record_checkpoints(64)
+        s.step(case.nsteps)
+        K, S, C = s.autotune_adjoint(rec, tg, ckpt_every=64)
+        assert (K, S, C) == (s.config(fdw.FDW_CFG_ADJ_TIME_BLOCK), s.config(fdw.FDW_CFG_ADJ_SEGMENT_ROWS),
+                             s.config(fdw.FDW_CFG_ADJ_LANE_COLUMNS))
+        narrow = 1 if dt == fdw.FDW_F64 else 2
+        assert (C == narrow and 2 <= K <= 6) or (C == 2 * narrow and 2 <= K <= 4)
+        assert " adj m0 " in cache.read_text()
+        g = s.adjoint(rec, tg, ckpt_every=64).cpu().numpy()
+        s.close()
+        tol = 1e-12 if dt == fdw.FDW_F64 else 1e-4
+        assert np.abs(g - g0).max() <= tol * np.abs(g0).max()
+    finally:
+        del os.environ["FDW_AUTOTUNE_CACHE"]
