@@ -63,6 +63,11 @@ def _load():
                                               ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_long, ctypes.c_int, _IP,
                                               _DP, ctypes.c_int, ctypes.POINTER(ctypes.c_long), _DP, _DP, _DP]
             lib.fdwref_forward_ld.restype = ctypes.c_int
+            lib.fdwref_adi_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, _DP, _DP, _DP, _DP, ctypes.c_long,
+                                               _DP, _DP]
+            lib.fdwref_adi_forward.restype = ctypes.c_int
+            lib.fdwref_tridiag.argtypes = [ctypes.c_int, _DP, _DP, _DP, _DP, _DP]
             lib.fdwref_misfit.argtypes = [ctypes.c_long, ctypes.c_int, _DP, _DP]
             lib.fdwref_misfit.restype = ctypes.c_double
             lib.fdwref_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -220,3 +225,30 @@ def adjoint(nx: int, ny: int, dx: float, dy: float, tau: float, h1, h2, u0, u1, 
     if rc != 0:
         raise ValueError(f"fdwref_adjoint failed ({rc})")
     return (g1, g2) if separate else g1
+
+
+def adi_forward(nx: int, ny: int, dx: float, dy: float, tau: float, sigma: float, h1, h2, u0, u1, nsteps: int):
+    """The implicit factorized scheme (Section 3.3 / Section 4); returns dict(u_prev, u_cur)."""
+    h1 = _f64(h1)
+    h2 = h1 if h2 is None else _f64(h2)
+    u0, u1 = _f64(u0), _f64(u1)
+    assert h1.shape == (ny, nx) and h2.shape == (ny, nx) and u0.shape == (ny, nx) and u1.shape == (ny, nx)
+    up = np.empty((ny, nx))
+    uc = np.empty((ny, nx))
+    rc = _load().fdwref_adi_forward(nx, ny, dx, dy, tau, sigma, _d(h1), _d(h2), _d(u0), _d(u1), int(nsteps),
+                                    _d(up), _d(uc))
+    if rc != 0:
+        raise ValueError(f"fdwref_adi_forward failed ({rc})")
+    return dict(u_prev=up, u_cur=uc)
+
+
+def adi_forward_case(case, sigma: float = 0.25, nsteps: Optional[int] = None):
+    n = case.nsteps if nsteps is None else nsteps
+    return adi_forward(case.nx, case.ny, case.dx, case.dy, case.tau, sigma, case.h1, case.h2, case.u0, case.u1, n)
+
+
+def tridiag(lo, di, up, rhs) -> np.ndarray:
+    lo, di, up, rhs = _f64(lo), _f64(di), _f64(up), _f64(rhs)
+    x = np.empty_like(rhs)
+    _load().fdwref_tridiag(int(rhs.size), _d(lo), _d(di), _d(up), _d(rhs), _d(x))
+    return x

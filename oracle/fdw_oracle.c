@@ -530,3 +530,142 @@ int fdwref_forward_ld(int nx, int ny, double dx, double dy, double tau, const do
     return 0;
 #undef LD_MARK
 }
+
+/* ------------------------------------------------------------------------------------------
+ * The implicit scheme of the 2D experiment (Section 3.3: an implicit finite-difference scheme
+ * whose linear systems are solved by cyclic reduction; Section 4, Table 1 times it on a GPU).
+ * The paper names the scheme only by reference; what is computed here is the factorized
+ * (alternating-direction) implicit scheme for u_tt = L1 u + L2 u, L1 = d_x(h1 d_x .),
+ * L2 = d_y(h2 d_y .):
+ *     (I - sigma tau^2 L1)(I - sigma tau^2 L2) (u^{n+1} - 2u^n + u^{n-1}) = tau^2 (L1 + L2) u^n,
+ * with the start  u^1 = u^0 + tau u1 + (1/2) w^0,  (I - sigma tau^2 L1)(I - sigma tau^2 L2) w^0 =
+ * tau^2 (L1 + L2) u^0 (sigma = 0 is the leapfrog scheme above; sigma >= 1/4 is unconditionally
+ * stable for constant coefficients).  Each factor is a set of independent tridiagonal systems,
+ * one per grid line, solved here by plain Gaussian elimination (the Thomas algorithm).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Solve the tridiagonal system  lo[k] x[k-1] + di[k] x[k] + up[k] x[k+1] = rhs[k], k = 0..n-1
+ * (lo[0] and up[n-1] unused) by forward elimination and back substitution; x may alias rhs.
+ * scratch: 2n doubles. */
+static void thomas(int n, const double* lo, const double* di, const double* up, const double* rhs, double* x,
+                   double* scratch)
+{
+    double* cp = scratch;
+    double* dp = scratch + n;
+    cp[0] = (n > 1) ? up[0] / di[0] : 0.0;
+    dp[0] = rhs[0] / di[0];
+    for (int k = 1; k < n; ++k) {
+        const double m = di[k] - lo[k] * cp[k - 1];
+        cp[k] = (k < n - 1) ? up[k] / m : 0.0;
+        dp[k] = (rhs[k] - lo[k] * dp[k - 1]) / m;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int k = n - 2; k >= 0; --k) x[k] = dp[k] - cp[k] * x[k + 1];
+}
+
+/* w = [(I - sigma tau^2 L1)(I - sigma tau^2 L2)]^{-1} r on interior nodes (0 on the ring):
+ * first the x lines (I - sigma tau^2 L1) z = r, then the y lines (I - sigma tau^2 L2) w = z. */
+static void adi_solve(int nx, int ny, double dx, double dy, double sigma, double tau, const double* hx,
+                      const double* hy, const double* r, double* w)
+{
+    const double gx = sigma * tau * tau / (dx * dx), gy = sigma * tau * tau / (dy * dy);
+    const int mx = nx - 2, my = ny - 2;
+    double* z = (double*)calloc((size_t)nx * (size_t)ny, sizeof(double));
+    int j;
+#pragma omp parallel for schedule(static)
+    for (j = 1; j <= ny - 2; ++j) {
+        double* lo = (double*)malloc(sizeof(double) * 6 * (size_t)mx);
+        double *di = lo + mx, *up = di + mx, *rhs = up + mx, *scr = rhs + mx;
+        for (int k = 0; k < mx; ++k) {
+            const int i = k + 1;
+            lo[k] = -gx * AT(hx, j, i - 1);
+            up[k] = -gx * AT(hx, j, i);
+            di[k] = 1.0 + gx * (AT(hx, j, i - 1) + AT(hx, j, i));
+            rhs[k] = AT(r, j, i);
+        }
+        thomas(mx, lo, di, up, rhs, rhs, scr);
+        for (int k = 0; k < mx; ++k) AT(z, j, k + 1) = rhs[k];
+        free(lo);
+    }
+    int i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < nx; ++i) {
+        if (i == 0 || i == nx - 1) {
+            for (int jj = 0; jj < ny; ++jj) AT(w, jj, i) = 0.0;
+            continue;
+        }
+        double* lo = (double*)malloc(sizeof(double) * 6 * (size_t)my);
+        double *di = lo + my, *up = di + my, *rhs = up + my, *scr = rhs + my;
+        for (int k = 0; k < my; ++k) {
+            const int jj = k + 1;
+            lo[k] = -gy * AT(hy, jj - 1, i);
+            up[k] = -gy * AT(hy, jj, i);
+            di[k] = 1.0 + gy * (AT(hy, jj - 1, i) + AT(hy, jj, i));
+            rhs[k] = AT(z, jj, i);
+        }
+        thomas(my, lo, di, up, rhs, rhs, scr);
+        AT(w, 0, i) = 0.0;
+        AT(w, ny - 1, i) = 0.0;
+        for (int k = 0; k < my; ++k) AT(w, k + 1, i) = rhs[k];
+        free(lo);
+    }
+    free(z);
+}
+
+int fdwref_adi_forward(int nx, int ny, double dx, double dy, double tau, double sigma, const double* h1,
+                       const double* h2, const double* u0, const double* u1, long nsteps, double* u_prev_out,
+                       double* u_cur_out)
+{
+    if (nx < 3 || ny < 3 || !(tau > 0.0) || !(sigma >= 0.0) || nsteps < 0 || !h1 || !h2 || !u0 || !u1) return -1;
+    const size_t n = (size_t)nx * (size_t)ny;
+    double* hx = (double*)malloc(sizeof(double) * n);
+    double* hy = (double*)malloc(sizeof(double) * n);
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* b = (double*)malloc(sizeof(double) * n);
+    double* c = (double*)malloc(sizeof(double) * n);
+    double* r = (double*)malloc(sizeof(double) * n);
+    double* w = (double*)malloc(sizeof(double) * n);
+    if (!hx || !hy || !a || !b || !c || !r || !w) {
+        free(hx); free(hy); free(a); free(b); free(c); free(r); free(w);
+        return -2;
+    }
+    fdwref_faces(nx, ny, h1, h2, hx, hy);
+    zero_ring_copy(nx, ny, u0, a);
+    double *prev = a, *cur = a, *next = b;
+    if (nsteps >= 1) {
+        /* start: u^1 = u^0 + tau u1 + w^0 / 2 */
+        fdwref_apply(nx, ny, dx, dy, hx, hy, a, r);
+        for (size_t k = 0; k < n; ++k) r[k] *= tau * tau;
+        adi_solve(nx, ny, dx, dy, sigma, tau, hx, hy, r, w);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int ring = (i == 0 || j == 0 || i == nx - 1 || j == ny - 1);
+                AT(b, j, i) = ring ? 0.0 : AT(a, j, i) + tau * AT(u1, j, i) + 0.5 * AT(w, j, i);
+            }
+        prev = a;
+        cur = b;
+        next = c;
+        for (long s = 1; s < nsteps; ++s) {
+            fdwref_apply(nx, ny, dx, dy, hx, hy, cur, r);
+            for (size_t k = 0; k < n; ++k) r[k] *= tau * tau;
+            adi_solve(nx, ny, dx, dy, sigma, tau, hx, hy, r, w);
+            for (size_t k = 0; k < n; ++k) next[k] = 2.0 * cur[k] - prev[k] + w[k];
+            double* t = prev;
+            prev = cur;
+            cur = next;
+            next = t;
+        }
+    }
+    if (u_prev_out) memcpy(u_prev_out, prev, sizeof(double) * n);
+    if (u_cur_out) memcpy(u_cur_out, cur, sizeof(double) * n);
+    free(hx); free(hy); free(a); free(b); free(c); free(r); free(w);
+    return 0;
+}
+
+/* The tridiagonal solver alone (for its own pins): x = T^{-1} rhs. */
+void fdwref_tridiag(int n, const double* lo, const double* di, const double* up, const double* rhs, double* x)
+{
+    double* scr = (double*)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
+    thomas(n, lo, di, up, rhs, x, scr);
+    free(scr);
+}

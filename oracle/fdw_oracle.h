@@ -72,6 +72,20 @@ int fdwref_adjoint(int nx, int ny, double dx, double dy, double tau, const doubl
                    const double* u0, const double* u1, long nsteps, int nrecv, const int* recv,
                    const double* trace_grad, long ckpt_every, double* grad_h1, double* grad_h2);
 
+/* The implicit factorized (alternating-direction) scheme of the 2D experiment (Section 3.3;
+ * Section 4, Table 1): (I - sigma tau^2 L1)(I - sigma tau^2 L2)(u^{n+1} - 2u^n + u^{n-1}) =
+ * tau^2 (L1 + L2) u^n with L1, L2 the x and y parts of the operator of fdwref_apply; start
+ * u^1 = u^0 + tau u1 + w^0/2 with w^0 the same solve applied to tau^2 A u^0.  Line systems solved
+ * by the Thomas algorithm.  u_prev_out/u_cur_out as in fdwref_forward.  Returns 0, -1 on bad
+ * arguments, -2 when memory runs out. */
+int fdwref_adi_forward(int nx, int ny, double dx, double dy, double tau, double sigma, const double* h1,
+                       const double* h2, const double* u0, const double* u1, long nsteps, double* u_prev_out,
+                       double* u_cur_out);
+
+/* x = T^{-1} rhs for the tridiagonal T with sub-diagonal lo[1..n-1], diagonal di, super-diagonal
+ * up[0..n-2] (the line solver of fdwref_adi_forward). */
+void fdwref_tridiag(int n, const double* lo, const double* di, const double* up, const double* rhs, double* x);
+
 /* Number of OpenMP threads the oracle runs on. */
 int fdwref_threads(void);
 

@@ -41,6 +41,14 @@ MUTANTS = {
     "ld_apply_dx_dy_swapped": ("(east + west) / dx2 + (north + south) / dy2", "(east + west) / dy2 + (north + south) / dx2"),
     "ld_faces_hy_from_h1": ("0.5L * ((ld_t)AT(h2, j, i) + (ld_t)AT(h2, j + 1, i))",
                             "0.5L * ((ld_t)AT(h1, j, i) + (ld_t)AT(h1, j + 1, i))"),
+    # the implicit factorized scheme and its line solver
+    "adi_start_drops_half": ("tau * AT(u1, j, i) + 0.5 * AT(w, j, i)", "tau * AT(u1, j, i) + AT(w, j, i)"),
+    "adi_offdiag_sign": ("up[k] = -gx * AT(hx, j, i);", "up[k] = gx * AT(hx, j, i);"),
+    "adi_y_face_index": ("lo[k] = -gy * AT(hy, jj - 1, i);", "lo[k] = -gy * AT(hy, jj, i);"),
+    "adi_x_uses_gy": ("di[k] = 1.0 + gx * (AT(hx, j, i - 1) + AT(hx, j, i));",
+                      "di[k] = 1.0 + gy * (AT(hx, j, i - 1) + AT(hx, j, i));"),
+    "thomas_elimination": ("const double m = di[k] - lo[k] * cp[k - 1];", "const double m = di[k] - up[k] * cp[k - 1];"),
+    "thomas_back_substitution": ("x[k] = dp[k] - cp[k] * x[k + 1];", "x[k] = dp[k] + cp[k] * x[k + 1];"),
 }
 
 
@@ -114,6 +122,44 @@ def _pins_pass() -> dict:
         out["p8"] = bool(np.abs(r8["u_cur"] - expect8).max() < 1e-13)
     except Exception:
         out["p8"] = False
+    # P9 the implicit scheme: anisotropic eigenmode with velocity beyond the explicit limit, the
+    # line solver against a dense solve, and the leapfrog limit at small tau with variable h1, h2
+    try:
+        s9 = 0.25
+        tau9 = 3.0 * 2.0 / math.sqrt(4 * h1c / ddx**2 + 4 * h2c / ddy**2)
+        mx9 = h1c * 4 / ddx**2 * math.sin(kk * math.pi / (2 * (nx - 1))) ** 2
+        my9 = h2c * 4 / ddy**2 * math.sin(ll * math.pi / (2 * (ny - 1))) ** 2
+        P9 = (1 + s9 * tau9 * tau9 * mx9) * (1 + s9 * tau9 * tau9 * my9)
+        th9 = math.acos(1.0 - tau9 * tau9 * (mx9 + my9) / (2.0 * P9))
+        r9 = oracle.adi_forward(nx, ny, ddx, ddy, tau9, s9, np.full((ny, nx), h1c), np.full((ny, nx), h2c), mode,
+                                v * mode, 60)
+        e9 = (math.cos(60 * th9) + tau9 * v / math.sin(th9) * math.sin(60 * th9)) * mode
+        ok9 = bool(np.abs(r9["u_cur"] - e9).max() < 1e-10)
+        rng9 = np.random.default_rng(9)
+        lo9, up9 = rng9.normal(size=9), rng9.normal(size=9)
+        di9 = np.abs(lo9) + np.abs(up9) + 1.0
+        b9 = rng9.normal(size=9)
+        T9 = np.diag(di9) + np.diag(lo9[1:], -1) + np.diag(up9[:-1], 1)
+        ok9 = ok9 and bool(np.abs(oracle.tridiag(lo9, di9, up9, b9) - np.linalg.solve(T9, b9)).max() < 1e-12)
+        n9 = 25
+        xx9, yy9, X9, Y9 = I.mesh(n9, n9)
+        d9 = 2.0 / (n9 - 1)
+        g1 = 1.0 + 0.6 * np.exp(-((X9 - 0.1) ** 2) / 0.05) + 0.2 * Y9
+        g2 = 0.8 + 0.3 * np.sin(2 * X9) * np.cos(Y9)
+        w0 = I.zero_ring(np.exp(-((X9 - 0.2) ** 2 + (Y9 + 0.1) ** 2) / 0.03))
+        # one start step: w0 = 2 (u^1 - u^0) solves (I - s t^2 L1)(I - s t^2 L2) w0 = t^2 A u^0; the factors
+        # are applied with the (separately pinned) leapfrog operator, L1 from (h1, 0), L2 from (0, h2)
+        t9 = 3.0 * d9
+        w9 = 2.0 * (oracle.adi_forward(n9, n9, d9, d9, t9, 0.25, g1, g2, w0, np.zeros_like(w0), 1)["u_cur"] - w0)
+        z0 = np.zeros_like(g1)
+        L1 = lambda f: oracle.apply(*oracle.faces(g1, z0), f, d9, d9)
+        L2 = lambda f: oracle.apply(*oracle.faces(z0, g2), f, d9, d9)
+        v9 = w9 - 0.25 * t9 * t9 * L2(w9)
+        res9 = v9 - 0.25 * t9 * t9 * L1(v9) - t9 * t9 * (L1(w0) + L2(w0))
+        ok9 = ok9 and bool(np.abs(res9).max() < 1e-11 * np.abs(w9).max())
+        out["p9"] = ok9
+    except Exception:
+        out["p9"] = False
     # P6 adjoint vs central FD, h1 != h2
     rng = np.random.default_rng(2)
     nx, ny, N = 12, 10, 20

@@ -527,3 +527,105 @@ def test_p7_symmetric_coordinates_bitwise():
         x = I.node_coords(n, -1.0, 1.0)
         assert np.array_equal(x[::-1], -x)
         assert x[0] == -1.0 and x[-1] == 1.0
+
+
+# ----------------------------------------------------------------------------- P9
+# The implicit factorized scheme of the 2D experiment (Section 3.3; Section 4, Table 1).
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 50, 257])
+def test_p9_tridiagonal_solver_against_dense_solve(n):
+    """The line solver against numpy's dense LU solve on random diagonally dominant systems."""
+    rng = np.random.default_rng(n)
+    lo, up = rng.normal(size=n), rng.normal(size=n)
+    di = np.abs(lo) + np.abs(up) + 0.5 + rng.uniform(size=n)
+    rhs = rng.normal(size=n)
+    T = np.diag(di) + np.diag(lo[1:], -1) + np.diag(up[:-1], 1)
+    x = oracle.tridiag(lo, di, up, rhs)
+    assert np.abs(x - np.linalg.solve(T, rhs)).max() <= 1e-13 * max(1.0, np.abs(x).max())
+
+
+@pytest.mark.parametrize("k,l,v,cfl", [(1, 1, 0.0, 5.0), (2, 3, 1.3, 5.0), (3, 2, 0.4, 0.7)])
+def test_p9_adi_discrete_eigenmode(k, l, v, cfl):
+    """Constant h1 != h2, dx != dy: the separable sine modes are eigenvectors of both line
+    operators, so the implicit scheme acts on a mode's amplitude by the scalar recurrence
+    P (a_{n+1} - 2 a_n + a_{n-1}) = -tau^2 (mu_x + mu_y) a_n, P = (1 + s tau^2 mu_x)(1 + s tau^2 mu_y),
+    whose solution with the start a_1 = 1 + tau v - tau^2 (mu_x + mu_y)/(2P) is
+    a_n = cos n theta + (tau v / sin theta) sin n theta, cos theta = 1 - tau^2 (mu_x + mu_y)/(2P) --
+    also at a time step 5x the explicit stability limit (sigma = 1/4)."""
+    nx, ny = 41, 29
+    h1c, h2c = 2.0, 0.7
+    x0, x1, y0, y1, dx, dy, mode, tau, _ = _eigen_case(nx, ny, h1c, h2c, k, l, v, cfl=min(cfl, 0.9))
+    tau = tau * cfl / min(cfl, 0.9)
+    s = 0.25
+    mx = h1c * 4.0 / dx**2 * math.sin(k * math.pi / (2 * (nx - 1))) ** 2
+    my = h2c * 4.0 / dy**2 * math.sin(l * math.pi / (2 * (ny - 1))) ** 2
+    P = (1 + s * tau * tau * mx) * (1 + s * tau * tau * my)
+    theta = math.acos(1.0 - tau * tau * (mx + my) / (2.0 * P))
+    N = 300
+    r = oracle.adi_forward(nx, ny, dx, dy, tau, s, np.full((ny, nx), h1c), np.full((ny, nx), h2c), mode, v * mode, N)
+    B = tau * v / math.sin(theta)
+    expect = (math.cos(N * theta) + B * math.sin(N * theta)) * mode
+    assert np.abs(r["u_cur"] - expect).max() <= 1e-11 * max(1.0, abs(B))
+
+
+def test_p9_adi_sigma_zero_is_leapfrog():
+    """sigma = 0 turns every line system into the identity: the leapfrog scheme, bit for bit."""
+    c = I.line_case(n=64, nsteps=80)
+    a = oracle.forward_case(c)["u_cur"]
+    b = oracle.adi_forward_case(c, sigma=0.0)["u_cur"]
+    assert np.array_equal(a, b)
+
+
+def _adi_variable_case(n=65, T=0.4):
+    x, y, X, Y = I.mesh(n, n)
+    h1 = 1.0 + 0.6 * np.exp(-((X - 0.1) ** 2) / 0.05) + 0.2 * Y
+    h2 = 0.8 + 0.3 * np.sin(2 * X) * np.cos(Y)
+    u0 = I.zero_ring(np.exp(-((X - 0.2) ** 2 + (Y + 0.1) ** 2) / 0.03))
+    u1 = I.zero_ring(0.3 * np.exp(-((X + 0.3) ** 2 + Y**2) / 0.05))
+    return n, 2.0 / (n - 1), h1, h2, u0, u1, T
+
+
+def test_p9_adi_second_order_in_time_to_the_leapfrog_limit():
+    """Variable h1 != h2: as tau -> 0 at a fixed grid the implicit and the leapfrog schemes
+    converge to the same semi-discrete solution, each at second order in tau; their difference
+    at tau, tau/2, tau/4 (tau at CFL 0.4) falls by about 4 per halving."""
+    n, d, h1, h2, u0, u1, T = _adi_variable_case()
+    tau0 = 0.4 * d / math.sqrt(2 * max(h1.max(), h2.max()))
+    diffs = []
+    for q in (1, 2, 4):
+        N = int(round(T / tau0)) * q
+        tau = T / N
+        a = oracle.adi_forward(n, n, d, d, tau, 0.25, h1, h2, u0, u1, N)["u_cur"]
+        b = oracle.forward(n, n, d, d, tau, h1, h2, u0, u1, N)["u_cur"]
+        diffs.append(np.abs(a - b).max())
+    r1, r2 = diffs[0] / diffs[1], diffs[1] / diffs[2]
+    assert 3.5 < r1 < 4.5 and 3.5 < r2 < 4.5, (diffs, r1, r2)
+
+
+def test_p9_adi_stable_far_beyond_the_explicit_limit():
+    """Variable h1 != h2 at 20x the explicit stability limit: the implicit solution stays bounded
+    over 400 steps while the leapfrog scheme at the same step blows up."""
+    n, d, h1, h2, u0, u1, _ = _adi_variable_case(n=49)
+    tau = 20.0 * d / math.sqrt(2 * max(h1.max(), h2.max()))
+    a = oracle.adi_forward(n, n, d, d, tau, 0.25, h1, h2, u0, u1, 400)["u_cur"]
+    assert np.isfinite(a).all() and np.abs(a).max() < 3.0 * np.abs(u0).max()
+    b = oracle.forward(n, n, d, d, tau, h1, h2, u0, u1, 60)["u_cur"]
+    assert not np.isfinite(b).all() or np.abs(b).max() > 1e6
+
+
+def test_p9_adi_line_factors_against_the_operator():
+    """The line systems are the factors of the operator: with variable h1 != h2 and a step far
+    beyond the explicit limit, w0 = 2 (u^1 - u^0) (u1 = 0) satisfies
+    (I - sigma tau^2 L1)(I - sigma tau^2 L2) w0 = tau^2 (L1 + L2) u^0, the factors applied with the
+    leapfrog oracle's operator (pinned by P1-P3): L1 with (h1, 0), L2 with (0, h2)."""
+    n, d, h1, h2, u0, _, _ = _adi_variable_case(n=41)
+    tau = 4.0 * d
+    s = 0.25
+    w = 2.0 * (oracle.adi_forward(n, n, d, d, tau, s, h1, h2, u0, np.zeros_like(u0), 1)["u_cur"] - u0)
+    z = np.zeros_like(h1)
+    L1 = lambda f: oracle.apply(*oracle.faces(h1, z), f, d, d)
+    L2 = lambda f: oracle.apply(*oracle.faces(z, h2), f, d, d)
+    v = w - s * tau * tau * L2(w)
+    res = v - s * tau * tau * L1(v) - tau * tau * (L1(u0) + L2(u0))
+    assert np.abs(res).max() <= 1e-12 * np.abs(w).max()
