@@ -285,6 +285,44 @@ int fdw_autotune_adjoint(fdw_ctx* ctx, int32_t member, const int32_t* recv_ij, i
  * since the previous call; the counters are then cleared.  ms and launches are host pointers. */
 int fdw_kernel_time(fdw_ctx* ctx, double* ms, int64_t* launches);
 
+/* ---- The implicit scheme of the paper's 2D experiment (Section 3.3; Section 4, Table 1) ----
+ * The paper solves its 2D problem with an implicit finite-difference scheme whose systems are
+ * solved by cyclic reduction, and times that solver on a GPU (Table 1).  This is such a solver:
+ * the factorized (alternating-direction) implicit scheme
+ *     (I - sigma tau^2 L1)(I - sigma tau^2 L2)(u^{n+1} - 2u^n + u^{n-1}) = tau^2 (L1 + L2) u^n,
+ * L1 = d_x(h1 d_x .), L2 = d_y(h2 d_y .) with the face coefficients and zero Dirichlet data of the
+ * explicit solver, start u^1 = u^0 + tau u1 + w^0/2 (w^0 the same solve applied to tau^2 A u^0);
+ * every factor is a set of tridiagonal systems, one per grid line, solved by cyclic reduction
+ * in LDS.  sigma >= 1/4 is unconditionally stable (constant coefficients: every mode); sigma = 0
+ * is the leapfrog scheme.  The state is carried as (u, du = u^n - u^{n-1}).  Limits: the padded
+ * line length 2^p - 1 >= max(nx, ny) - 2 must fit four arrays in LDS (nx, ny <= 4097 in FP64,
+ * 8193 in FP32 on gfx950; FDW_ENOTSUP beyond). */
+typedef struct fdw_adi fdw_adi; /* opaque */
+
+/* Device workspace (bytes) of one implicit solver for problem p (0 if p is invalid). */
+size_t fdw_adi_workspace_bytes(const fdw_problem* p);
+
+/* Create an implicit solver at step 0: p as for fdw_init (one member); sigma >= 0 the implicit
+ * weight (0.25 recommended); workspace as for fdw_init (256-byte aligned, caller-owned);
+ * u0, u1, h1: device [ny][nx] in the storage type; h2 device or NULL (h2 = h1).  h is validated
+ * (finite, > 0, or >= 0 with FDW_ALLOW_ZERO_H) and for sigma < 1/4 the stability bound
+ * tau^2 (4 max hx/dx^2 + 4 max hy/dy^2)(1 - 4 sigma) <= 4 is checked (FDW_ECFL; skipped with
+ * FDW_ALLOW_UNSTABLE); both read results back, so this call synchronises the stream. */
+int fdw_adi_init(const fdw_problem* p, double sigma, void* workspace, size_t ws_bytes, const void* u0, const void* u1,
+                 const void* h1, const void* h2, void* hip_stream, fdw_adi** out);
+
+/* Advance by n >= 0 steps (the start step first when at step 0); asynchronous. */
+int fdw_adi_step_n(fdw_adi* s, int64_t n);
+
+/* Copy (u^n, du^n) to device buffers [ny][nx] (either may be NULL) and the step counter to *n. */
+int fdw_adi_get_state(fdw_adi* s, void* u, void* du, int64_t* n);
+
+/* Return to step 0. */
+int fdw_adi_reset(fdw_adi* s);
+
+const char* fdw_adi_last_error(const fdw_adi* s);
+void fdw_adi_destroy(fdw_adi* s);
+
 /* Error reporting and teardown (no passage: execution control).  fdw_last_error: one line on the
  * context's last failure (owned by the context, valid until its next call); fdw_status_string:
  * static text of a status code; fdw_destroy: releases the host side of a context (the caller

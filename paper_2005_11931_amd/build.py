@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libfdw.so")
-SOURCES = ["fdw_api.hip", "fdw_kernels.hip", "fdw_adjoint.hip", "fdw_noalloc.hip", "fdw_step_f32c4.hip", "fdw_step_f32c2.hip",
+SOURCES = ["fdw_api.hip", "fdw_kernels.hip", "fdw_adjoint.hip", "fdw_noalloc.hip", "fdw_implicit.hip", "fdw_step_f32c4.hip", "fdw_step_f32c2.hip",
            "fdw_step_f64c2.hip", "fdw_step_f64c1.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

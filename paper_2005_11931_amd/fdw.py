@@ -38,6 +38,8 @@ EXPORTED = [
     "fdw_member_distance",
     "fdw_steps_taken", "fdw_configure", "fdw_get_config", "fdw_autotune", "fdw_kernel_time", "fdw_last_error",
     "fdw_status_string", "fdw_destroy", "fdw_misfit_noalloc", "fdw_noalloc_last_error", "fdw_autotune_adjoint",
+    "fdw_adi_workspace_bytes", "fdw_adi_init", "fdw_adi_step_n", "fdw_adi_get_state", "fdw_adi_reset",
+    "fdw_adi_last_error", "fdw_adi_destroy",
 ]
 
 
@@ -81,6 +83,21 @@ _lib.fdw_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64
 _lib.fdw_autotune_adjoint.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp,
                                       ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.fdw_autotune_adjoint.restype = ctypes.c_int
+_lib.fdw_adi_workspace_bytes.argtypes = [ctypes.POINTER(fdw_problem)]
+_lib.fdw_adi_workspace_bytes.restype = ctypes.c_size_t
+_lib.fdw_adi_init.argtypes = [ctypes.POINTER(fdw_problem), ctypes.c_double, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp,
+                              _vp, ctypes.POINTER(_vp)]
+_lib.fdw_adi_init.restype = ctypes.c_int
+_lib.fdw_adi_step_n.argtypes = [_vp, ctypes.c_int64]
+_lib.fdw_adi_step_n.restype = ctypes.c_int
+_lib.fdw_adi_get_state.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]
+_lib.fdw_adi_get_state.restype = ctypes.c_int
+_lib.fdw_adi_reset.argtypes = [_vp]
+_lib.fdw_adi_reset.restype = ctypes.c_int
+_lib.fdw_adi_last_error.argtypes = [_vp]
+_lib.fdw_adi_last_error.restype = ctypes.c_char_p
+_lib.fdw_adi_destroy.argtypes = [_vp]
+_lib.fdw_adi_destroy.restype = None
 _lib.fdw_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.fdw_kernel_time.restype = ctypes.c_int
 _lib.fdw_last_error.argtypes = [_vp]
@@ -336,6 +353,69 @@ def misfit_noalloc(traces: torch.Tensor, d: torch.Tensor, J_out: torch.Tensor,
                                  _vp(_stream_handle(traces.device)))
     if st != 0:
         raise FdwError(st, _lib.fdw_noalloc_last_error().decode())
+
+
+class ImplicitSolver:
+    """The implicit factorized scheme with cyclic-reduction line solves (fdw_adi_*)."""
+
+    def __init__(self, problem: fdw_problem, sigma: float, u0: torch.Tensor, u1: torch.Tensor, h1: torch.Tensor,
+                 h2: Optional[torch.Tensor] = None, device: str = "cuda:0"):
+        self.device = torch.device(device)
+        self.problem = problem
+        self.tdtype = torch_dtype(problem.dtype)
+        ws = _lib.fdw_adi_workspace_bytes(ctypes.byref(problem))
+        if ws == 0:
+            raise FdwError(FDW_EINVAL, "invalid problem description")
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self._keep = [t.contiguous() for t in (u0, u1, h1) + (() if h2 is None else (h2,))]
+        for t in self._keep:
+            assert t.dtype == self.tdtype and tuple(t.shape) == (problem.ny, problem.nx), (t.dtype, t.shape)
+        ctx = _vp()
+        st = _lib.fdw_adi_init(ctypes.byref(problem), float(sigma), _vp(self.workspace.data_ptr()), ws,
+                               _ptr(self._keep[0]), _ptr(self._keep[1]), _ptr(self._keep[2]),
+                               None if h2 is None else _ptr(self._keep[3]), _vp(_stream_handle(self.device)),
+                               ctypes.byref(ctx))
+        if st != 0:
+            raise FdwError(st, "fdw_adi_init failed")
+        self.ctx = ctx
+
+    def _check(self, st: int):
+        if st != 0:
+            raise FdwError(st, _lib.fdw_adi_last_error(self.ctx).decode())
+
+    def step(self, n: int):
+        self._check(_lib.fdw_adi_step_n(self.ctx, int(n)))
+
+    def get_state(self) -> Tuple[torch.Tensor, torch.Tensor, int]:
+        p = self.problem
+        u = torch.empty((p.ny, p.nx), dtype=self.tdtype, device=self.device)
+        du = torch.empty_like(u)
+        n = ctypes.c_int64()
+        self._check(_lib.fdw_adi_get_state(self.ctx, _ptr(u), _ptr(du), ctypes.byref(n)))
+        return u, du, int(n.value)
+
+    def reset(self):
+        self._check(_lib.fdw_adi_reset(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            torch.cuda.synchronize(self.device)
+            _lib.fdw_adi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def implicit_solver_for_case(case, sigma: float = 0.25, dtype: int = FDW_F64, device: str = "cuda:0",
+                             flags: int = 0) -> ImplicitSolver:
+    td = torch_dtype(dtype)
+    t = lambda a: torch.as_tensor(a, dtype=td, device=device)
+    return ImplicitSolver(problem_from_case(case, dtype, flags), sigma, t(case.u0), t(case.u1), t(case.h1),
+                          None if case.h2 is None else t(case.h2), device=device)
 
 
 def solver_for_case(case, dtype: int = FDW_F64, device: str = "cuda:0", flags: int = 0, separate_h2: bool = False):

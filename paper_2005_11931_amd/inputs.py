@@ -517,3 +517,17 @@ def paper_case1_eps_sweep(eps_list: Sequence[float] = (0.8, 0.5, 0.2, 0.1, 0.05,
     regularisation widths the paper compares at t = 5, in row mode; all members share dx and
     tau (the depth lies in [10, 100] for every eps)."""
     return [paper_1d_case("jump", eps=e, dx=dx, T=T) for e in eps_list]
+
+
+def paper_table1_case(n: int, dt: float = 0.05, T: float = 5.0, eps: float = 0.8) -> Case:
+    """The workload of the paper's GPU timings (Section 4, Table 1): the Section 3.3 problem on an
+    n x n node grid of [0, 100]^2 (dx = dy = 100/(n-1)), H_eps = h_{0,eps}(x), u0 = 50 exp(-((x-40)^2
+    + (y-50)^2)/8), u1 = 0, time step dt = 0.05 and T = 5 (100 steps), as the table states."""
+    x = node_coords(n, 0.0, 100.0)
+    hx = paper_depth_1d(x, eps, "jump")
+    H = np.broadcast_to(hx[None, :], (n, n)).copy()
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = zero_ring(50.0 * np.exp(-((X - 40.0) ** 2 + (Y - 50.0) ** 2) / 8.0))
+    N = int(round(T / dt))
+    return Case(f"table1-{n}", n, n, 0.0, 100.0, 0.0, 100.0, T / N, N, H, None, u0, np.zeros_like(u0),
+                meta=dict(eps=eps, dt=dt))

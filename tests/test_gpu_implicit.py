@@ -1,0 +1,161 @@
+"""The implicit scheme of the paper's 2D experiment (Section 3.3; Section 4, Table 1): the
+factorized alternating-direction scheme with cyclic-reduction line solves on the GPU, through the
+C-ABI (fdw_adi_*), against the oracle's Thomas-algorithm evaluation of the same scheme.
+
+Bars: FP64 max-abs within 1e-12 of the amplitude of the data (the solution scales with it);
+FP32 relative error max|u32 - u64| / max|u64| within 1e-5; sigma = 0 against the leapfrog oracle;
+the exact discrete eigenmode at five times the explicit stability limit."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_11931_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _variable_case(nx, ny, N, cfl):
+    x, y, X, Y = I.mesh(nx, ny)
+    h1 = 1.0 + 0.6 * np.exp(-((X - 0.1) ** 2) / 0.05) + 0.2 * Y
+    h2 = 0.8 + 0.3 * np.sin(2 * X) * np.cos(Y)
+    u0 = I.zero_ring(np.exp(-((X - 0.2) ** 2 + (Y + 0.1) ** 2) / 0.03))
+    u1 = I.zero_ring(0.3 * np.exp(-((X + 0.3) ** 2 + Y**2) / 0.05))
+    dx, dy = 2.0 / (nx - 1), 2.0 / (ny - 1)
+    tau = cfl / math.sqrt(4 * h1.max() / dx**2 + 4 * h2.max() / dy**2) * 2.0
+    return I.Case("adi", nx, ny, -1, 1, -1, 1, tau, N, h1, h2, u0, u1)
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (37, 53), (257, 131), (5, 700), (1030, 66), (513, 513)])
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_adi_vs_oracle(nx, ny, dtype_name):
+    """Ragged sizes (line lengths around powers of two, single unknowns, long thin grids),
+    h1 != h2 varying in x and y, a step 3x the explicit limit."""
+    from paper_2005_11931_amd import fdw
+
+    dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
+    case = _variable_case(nx, ny, 60, cfl=3.0)
+    _say("adi", nx, ny, dtype_name)
+    s = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=dt)
+    s.step(25)
+    s.step(35)
+    u, du, n = s.get_state()
+    s.close()
+    assert n == 60
+    ref = oracle.adi_forward_case(case, sigma=0.25)
+    u = u.cpu().numpy().astype(np.float64)
+    du = du.cpu().numpy().astype(np.float64)
+    amp = np.abs(case.u0).max()
+    if dt == fdw.FDW_F64:
+        assert np.abs(u - ref["u_cur"]).max() <= 1e-12 * amp
+        assert np.abs(du - (ref["u_cur"] - ref["u_prev"])).max() <= 1e-12 * amp
+    else:
+        assert np.abs(u - ref["u_cur"]).max() <= 1e-5 * max(np.abs(ref["u_cur"]).max(), 1e-300)
+
+
+def test_adi_sigma_zero_is_the_leapfrog_scheme():
+    from paper_2005_11931_amd import fdw
+
+    case = I.line_case(n=96, nsteps=120)
+    s = fdw.implicit_solver_for_case(case, sigma=0.0, dtype=fdw.FDW_F64)
+    s.step(120)
+    u = s.get_state()[0].cpu().numpy()
+    s.close()
+    assert np.abs(u - oracle.forward_case(case)["u_cur"]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("k,l,v", [(1, 1, 0.0), (2, 3, 1.3)])
+def test_adi_eigenmode_beyond_the_explicit_limit(k, l, v):
+    """Constant h1 != h2, dx != dy, 5x the explicit stability limit: the exact discrete
+    eigenmode (cos n theta + (tau v / sin theta) sin n theta) mode with
+    cos theta = 1 - tau^2 (mu_x + mu_y) / (2 (1 + s tau^2 mu_x)(1 + s tau^2 mu_y))."""
+    from paper_2005_11931_amd import fdw
+
+    nx, ny = 65, 47
+    x0, x1, y0, y1 = 0.0, 1.3, -0.5, 0.5
+    dx, dy = (x1 - x0) / (nx - 1), (y1 - y0) / (ny - 1)
+    h1c, h2c, s = 2.0, 0.7, 0.25
+    mode = np.outer(np.sin(l * math.pi * np.arange(ny) / (ny - 1)), np.sin(k * math.pi * np.arange(nx) / (nx - 1)))
+    tau = 5.0 * 2.0 / math.sqrt(4 * h1c / dx**2 + 4 * h2c / dy**2)
+    mx = h1c * 4.0 / dx**2 * math.sin(k * math.pi / (2 * (nx - 1))) ** 2
+    my = h2c * 4.0 / dy**2 * math.sin(l * math.pi / (2 * (ny - 1))) ** 2
+    P = (1 + s * tau * tau * mx) * (1 + s * tau * tau * my)
+    theta = math.acos(1.0 - tau * tau * (mx + my) / (2.0 * P))
+    N = 200
+    case = I.Case("mode", nx, ny, x0, x1, y0, y1, tau, N, np.full((ny, nx), h1c), np.full((ny, nx), h2c),
+                  I.zero_ring(mode), I.zero_ring(v * mode))
+    sv = fdw.implicit_solver_for_case(case, sigma=s, dtype=fdw.FDW_F64)
+    sv.step(N)
+    u = sv.get_state()[0].cpu().numpy()
+    sv.close()
+    B = tau * v / math.sin(theta)
+    expect = (math.cos(N * theta) + B * math.sin(N * theta)) * mode
+    assert np.abs(u - expect).max() <= 1e-11 * max(1.0, abs(B))
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_table1_workload_vs_oracle(n):
+    """The Table 1 workload (Section 4: [0, 100]^2, dt = 0.05, T = 5, 100 steps) at 256^2 and
+    512^2 in FP64 against the oracle; also FP32."""
+    from paper_2005_11931_amd import fdw
+
+    case = I.paper_table1_case(n)
+    _say("table1", n)
+    ref = oracle.adi_forward_case(case, sigma=0.25)["u_cur"]
+    for dt in (fdw.FDW_F64, fdw.FDW_F32):
+        s = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=dt)
+        s.step(case.nsteps)
+        u = s.get_state()[0].cpu().numpy().astype(np.float64)
+        s.close()
+        err = np.abs(u - ref).max()
+        _say("dtype", dt, "max-abs", err)
+        assert err <= (1e-12 if dt == fdw.FDW_F64 else 1e-5) * 50.0
+
+
+def test_adi_section_3_3_at_the_papers_time_step():
+    """Section 3.3 at the paper's own resolution and time step (2001^2, dx = 0.05, dt = 0.5, T = 5:
+    10 steps, 140x the explicit limit) against the oracle: stable, and equal to rounding."""
+    from paper_2005_11931_amd import fdw
+
+    base = I.paper_2d_case()
+    case = I.Case(**{**base.__dict__, "tau": 0.5, "nsteps": 10})
+    ref = oracle.adi_forward_case(case, sigma=0.25)["u_cur"]
+    s = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=fdw.FDW_F64)
+    s.step(10)
+    u = s.get_state()[0].cpu().numpy()
+    s.close()
+    assert np.isfinite(u).all() and np.abs(u).max() < 2 * 50.0
+    assert np.abs(u - ref).max() <= 1e-12 * 50.0
+
+
+def test_adi_errors():
+    import torch
+
+    from paper_2005_11931_amd import fdw
+
+    case = I.line_case(n=64, nsteps=10)
+    big = I.Case(**{**case.__dict__, "tau": case.tau * 4})
+    # below sigma = 1/4 the time step is checked
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.implicit_solver_for_case(big, sigma=0.0, dtype=fdw.FDW_F64)
+    assert e.value.status == fdw.FDW_ECFL
+    fdw.implicit_solver_for_case(big, sigma=0.25, dtype=fdw.FDW_F64).close()
+    bad = case.h1.copy()
+    bad[3, 3] = float("nan")
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.implicit_solver_for_case(I.Case(**{**case.__dict__, "h1": bad}), dtype=fdw.FDW_F64)
+    assert e.value.status == fdw.FDW_EINVAL
+    # lines too long for the LDS of one workgroup in FP64
+    p = fdw.problem(9000, 5, 1e-3, 10, fdw.FDW_F64)
+    assert fdw.lib().fdw_adi_workspace_bytes(p) > 0
+    z = torch.zeros((5, 9000), dtype=torch.float64, device="cuda")
+    with pytest.raises(fdw.FdwError) as e:
+        fdw.ImplicitSolver(p, 0.25, z, z, z + 1.0)
+    assert e.value.status == fdw.FDW_ENOTSUP
