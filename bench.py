@@ -373,6 +373,70 @@ def _time_gradient(fdw, torch, s, case, rec, tg, steps, warmup, tune=False):
                 grad_max=float(g.abs().max()), grad=g.cpu().numpy(), adj_tuned=tuned)
 
 
+# The paper's GPU timings (Section 4, Table 1): cyclic-reduction implicit solver, 100 steps of the
+# Section 3.3 problem (dt = 0.05, T = 5) on N x N grids; serial CPU (i7-9800X) and RTX 2080 Ti
+# seconds as printed.
+TABLE1 = {256: (0.91, 0.88), 512: (3.73, 2.07), 1024: (15.92, 7.16), 2048: (64.8, 20.30), 4096: (280.54, 62.76)}
+
+
+def table1_bench(fdw, torch, I, steps, oracle_budget_s=2.0):
+    """Table 1's workload on this GPU: the implicit solver (factorized scheme, cyclic-reduction line
+    solves) for the 100 steps of the table, FP64 and FP32, beside the FP64 oracle of the same scheme
+    on the host cores (all 100 steps where that takes under oracle_budget_s, else the first k steps
+    with the time scaled linearly to 100, stated per row) and the explicit leapfrog solver run to the
+    same T = 5 at CFL 0.5."""
+    import oracle
+
+    rows = []
+    for n in sorted(TABLE1):
+        case = I.paper_table1_case(n)
+        N = case.nsteps
+        row = {"n": n, "steps": N, "paper_cpu_s": TABLE1[n][0], "paper_gpu_s": TABLE1[n][1]}
+        for dt, name in ((fdw.FDW_F64, "f64"), (fdw.FDW_F32, "f32")):
+            s = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=dt)
+            s.step(N)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(max(1, steps)):
+                s.reset()
+                s.step(N)
+            torch.cuda.synchronize()
+            row[f"gpu_{name}_s"] = (time.perf_counter() - t0) / max(1, steps)
+            s.close()
+        # explicit leapfrog to the same T at CFL 0.5 (FP32)
+        dx = 100.0 / (n - 1)
+        tau0 = 0.5 * dx / math.sqrt(float(case.h1.max()))
+        Ne = int(math.ceil(5.0 / tau0))
+        lf = I.Case(**{**case.__dict__, "tau": 5.0 / Ne, "nsteps": Ne})
+        s = fdw.solver_for_case(lf, dtype=fdw.FDW_F32)
+        s.step(Ne)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.reset()
+        s.step(Ne)
+        torch.cuda.synchronize()
+        row["leapfrog_f32_s"] = time.perf_counter() - t0
+        row["leapfrog_steps"] = Ne
+        s.close()
+        # the oracle of the implicit scheme (FP64, all host threads)
+        t0 = time.perf_counter()
+        oracle.adi_forward_case(case, nsteps=2)
+        t2 = time.perf_counter() - t0
+        k = N if t2 * N / 2 <= oracle_budget_s else max(2, int(oracle_budget_s / (t2 / 2)))
+        t0 = time.perf_counter()
+        oracle.adi_forward_case(case, nsteps=k)
+        to = (time.perf_counter() - t0) * N / k
+        row["oracle_s"] = to
+        row["oracle_steps_run"] = k
+        row["speedup_f64_vs_oracle"] = to / row["gpu_f64_s"]
+        row["speedup_f64_vs_paper_gpu"] = TABLE1[n][1] / row["gpu_f64_s"]
+        row["gpu_f64_updates_per_s"] = (n - 2) ** 2 * N / row["gpu_f64_s"]
+        rows.append({k2: (round(v, 6) if isinstance(v, float) else v) for k2, v in row.items()})
+        log(json.dumps(rows[-1]))
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cpu_baseline(I, budget_s=15.0):
     """The FP64 oracle on the host cores: first k steps of the same 8192^2 workload, k chosen
     from two calibration runs (3 and 13 steps; their difference removes the per-call set-up)
@@ -744,6 +808,16 @@ def main():
                                                        "receivers on the row nearest y = 0.075, seeded trace "
                                                        "gradient, checkpoints every 64 steps"}}
         torch.cuda.empty_cache()
+    if not args.skip_extra:
+        log("table 1 workload: implicit solver")
+        out["table1_implicit"] = {
+            "rows": table1_bench(fdw, torch, I, min(3, max(1, args.steps - 1))),
+            "workload": "Section 4 Table 1: Section 3.3 problem on N x N nodes of [0,100]^2, eps = 0.8, dt = 0.05, "
+                        "T = 5 (100 steps); implicit factorized scheme (sigma = 1/4) with cyclic-reduction line "
+                        "solves on this GPU (FP64 and FP32); paper_*_s: the paper's serial CPU and RTX 2080 Ti "
+                        "times for its cyclic-reduction solver (context, other hardware and code); oracle_s: the "
+                        "FP64 oracle of the same scheme on the host cores (Thomas algorithm; linear in the steps "
+                        "when truncated); leapfrog_f32_s: the explicit solver to the same T at CFL 0.5"}
     if not args.skip_cpu:
         log("cpu baseline")
         cb, case, k, u_ref = cpu_baseline(I)
