@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--ski
        python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: three 800-step
                         forward solves plus three plain copies used to calibrate the counters)
        python bench.py --profile-run --adjoint   (short run of the reverse sweep for rocprofv3)
+       python bench.py --profile-run --workload bathymetry16384|family|implicit4096   (other short runs)
        python bench.py --summarize-profile DIR [DIR ...] --out NAME (writes profiles/NAME.txt,
                         and NAME.json with calibrated bytes per launch, from rocprofv3 CSV files)
 """
@@ -499,23 +500,28 @@ def oracle_single_thread_rate(I, n=2048, steps=20):
         return None
 
 
-def profile_run(dtype_name: str):
+def profile_run(dtype_name: str, workload: str = "point8192"):
     """Short, profiler-friendly run: three 800-step forward solves of the 8192^2 workload with
-    per-step energy (the configuration the bench times), then three state read-outs: each is a
-    plain copy kernel (k_copy_out) that reads and writes exactly n*n words, used to calibrate
-    the memory counters."""
+    per-step energy (the configuration the bench times; workload bathymetry16384: three 400-step
+    solves of the 16384^2 case in its autotuned configuration, no energy), then three state
+    read-outs: each is a plain copy kernel (k_copy_out) that reads and writes exactly n*n words,
+    used to calibrate the memory counters."""
     import torch
 
     from paper_2005_11931_amd import fdw
     from paper_2005_11931_amd import inputs as I
 
     dtype = fdw.FDW_F32 if dtype_name == "f32" else fdw.FDW_F64
-    case = I.point_case(n=8192, nsteps=5000)
+    big = workload == "bathymetry16384"
+    case = I.bathymetry_case(n=16384, nsteps=10000) if big else I.point_case(n=8192, nsteps=5000)
     s = fdw.solver_for_case(case, dtype=dtype)
     del case
-    for _ in range(3):  # three 800-step solves: the average is over ~300 launches, warm-up included
+    if big:
+        s.configure(fdw.FDW_CFG_TIME_BLOCK, 8)  # the autotuner's choice on this workload (bench line)
+        s.configure(fdw.FDW_CFG_SEGMENT_ROWS, 64)
+    for _ in range(3):  # three solves: the average is over ~150-300 launches, warm-up included
         s.reset()
-        s.step(800, energy=True)
+        s.step(400 if big else 800, energy=not big)
     torch.cuda.synchronize()
     for _ in range(3):
         s.get_state()
@@ -523,6 +529,41 @@ def profile_run(dtype_name: str):
     log("profile run done:", dtype_name, "K", s.config(fdw.FDW_CFG_TIME_BLOCK), "C",
         s.config(fdw.FDW_CFG_LANE_COLUMNS), "S", s.config(fdw.FDW_CFG_SEGMENT_ROWS))
     s.close()
+
+
+def profile_run_family():
+    """Short run of the 32-member family for rocprofv3: 400 steps with energies, once with one
+    launch per time block, once with the persistent launch."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+    from paper_2005_11931_amd import inputs as I
+
+    fam = I.family()
+    for persistent in (0, 1):
+        s = fdw.family_solver(fam, dtype=fdw.FDW_F32)
+        s.configure(fdw.FDW_CFG_BATCH_MODE, persistent)
+        s.step(400, energy=True)
+        torch.cuda.synchronize()
+        s.close()
+    log("family profile run done")
+
+
+def profile_run_implicit():
+    """Short run of the implicit solver for rocprofv3: the Table 1 workload at 4096^2, 20 steps in
+    FP64 and in FP32."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+    from paper_2005_11931_amd import inputs as I
+
+    case = I.paper_table1_case(4096)
+    for dt in (fdw.FDW_F64, fdw.FDW_F32):
+        s = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=dt)
+        s.step(20)
+        torch.cuda.synchronize()
+        s.close()
+    log("implicit profile run done")
 
 
 def profile_run_adjoint():
@@ -548,7 +589,7 @@ def profile_run_adjoint():
     s.close()
 
 
-def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32", factors=None):
+def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32", factors=None, n: int = 8192):
     """Collects kernel statistics and FETCH_SIZE / WRITE_SIZE counter rows from rocprofv3 CSV
     output under `dirs` into profiles/<name>.txt.  When both counters were taken for the
     streaming kernel and for the calibration copy (k_copy_out: n*n words read and written per
@@ -597,7 +638,6 @@ def summarize_profile(dirs, name: str, command: str, dtype_name: str = "f32", fa
     need = [("copy", "FETCH_SIZE"), ("copy", "WRITE_SIZE"), ("k_step", "FETCH_SIZE"), ("k_step", "WRITE_SIZE")]
     if all(k in summary for k in need):
         mean = {k: sum(summary[k]) / len(summary[k]) for k in need}
-        n = 8192
         es = 4 if dtype_name == "f32" else 8
         copy_kib = n * n * es / 1024.0
         f_fetch = copy_kib / mean[("copy", "FETCH_SIZE")]
@@ -627,19 +667,26 @@ def main():
         ap.add_argument("--command", default="")
         ap.add_argument("--dtype", default="f32")
         ap.add_argument("--factors", nargs=2, type=float, default=None)
+        ap.add_argument("--n", type=int, default=8192)
         a = ap.parse_args()
-        summarize_profile(a.summarize_profile, a.out, a.command, a.dtype, a.factors)
+        summarize_profile(a.summarize_profile, a.out, a.command, a.dtype, a.factors, a.n)
         return
     if "--profile-run" in sys.argv:
         ap = argparse.ArgumentParser()
         ap.add_argument("--profile-run", action="store_true")
         ap.add_argument("--dtype", default="f32")
         ap.add_argument("--adjoint", action="store_true")
+        ap.add_argument("--workload", default="point8192",
+                        choices=["point8192", "bathymetry16384", "family", "implicit4096"])
         a = ap.parse_args()
         if a.adjoint:
             profile_run_adjoint()
+        elif a.workload == "family":
+            profile_run_family()
+        elif a.workload == "implicit4096":
+            profile_run_implicit()
         else:
-            profile_run(a.dtype)
+            profile_run(a.dtype, a.workload)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
