@@ -199,6 +199,16 @@ def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(1, steps)
     K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    policy = s.config(fdw.FDW_CFG_STREAM_POLICY)
+    # the dominant kernel's average launch (HIP events on the solver's stream) over one more
+    # solve, against the algorithmic bytes of a launch (5 words per node)
+    s.configure(fdw.FDW_CFG_TIMING, 1)
+    s.kernel_time()
+    one()
+    ms, launches = s.kernel_time()
+    s.configure(fdw.FDW_CFG_TIMING, 0)
+    launch_ms = ms / max(launches, 1)
+    kernel_gbs = 5 * 4 * n * n / (launch_ms * 1e-3) / 1e9
     par = {}
     if parity:
         u32 = s.get_state()[0].cpu().numpy()
@@ -223,7 +233,8 @@ def largest_bench(fdw, torch, I, steps, warmup=1, parity=True):
         del h
     torch.cuda.empty_cache()
     crop = adjoint_crop_bench(fdw, torch, I, case, max(1, steps), warmup, parity=parity)
-    return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par, tuned=tuned, tune_s=tune_s)
+    return dict(ups=updates / dt, sec=dt, K=K, crop=crop, parity=par, tuned=tuned, tune_s=tune_s, policy=policy,
+                launch_ms=launch_ms, kernel_gbs=kernel_gbs)
 
 
 def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, fp64_smallest=0, tune=False):
@@ -259,13 +270,14 @@ def family_bench(fdw, torch, I, steps, warmup, persistent=False, energy=False, f
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     K = s.config(fdw.FDW_CFG_TIME_BLOCK)
+    policy = s.config(fdw.FDW_CFG_STREAM_POLICY)
     drift = None
     if energy:
         E = e.cpu().numpy()
         drift = float(max(abs(E[m] - E[m][0]).max() / E[m][0] for m in range(E.shape[0])))
     s.close()
     return dict(sec=dt, updates=updates, ups=updates / dt, members=32, K=K, alg_GBs=bytes_alg / dt / 1e9,
-                energy_drift=drift, tuned=tuned)
+                energy_drift=drift, tuned=tuned, policy=policy)
 
 
 def adjoint_bench(fdw, torch, I, steps, warmup):
@@ -517,8 +529,10 @@ def profile_run(dtype_name: str, workload: str = "point8192"):
     s = fdw.solver_for_case(case, dtype=dtype)
     del case
     if big:
-        s.configure(fdw.FDW_CFG_TIME_BLOCK, 8)  # the autotuner's choice on this workload (bench line)
+        # the autotuner's choice on this workload (bench line)
+        s.configure(fdw.FDW_CFG_TIME_BLOCK, 8)
         s.configure(fdw.FDW_CFG_SEGMENT_ROWS, 64)
+        s.configure(fdw.FDW_CFG_STREAM_POLICY, 3)
     for _ in range(3):  # three solves: the average is over ~150-300 launches, warm-up included
         s.reset()
         s.step(400 if big else 800, energy=not big)
@@ -786,6 +800,7 @@ def main():
         out["batched"] = {"value": round(fam["ups"], 1), "unit": "grid-point updates/s", "members": 32,
                           "ms_per_step": round(fam["sec"] * 1e3, 2), "time_block": fam["K"],
                           "autotuned_time_block_segment_rows_lane_columns": fam["tuned"],
+                          "autotuned_stream_policy": fam["policy"],
                           "alg_GBs": round(fam["alg_GBs"], 1), "frac": round(fam["alg_GBs"] / HBM_PEAK_GBS, 4),
                           "energy_value": round(fame["ups"], 1),
                           "energy_frac": round(fame["alg_GBs"] / HBM_PEAK_GBS, 4),
@@ -797,8 +812,8 @@ def main():
                           "mixed_fp64_smallest4_energy_ms_per_step": round(famx["sec"] * 1e3, 2),
                           "workload": "32 regularisations, eps log-spaced 0.1 .. 2dx, delta line / Heaviside jump, "
                                       "512^2-4096^2, 2000 steps, FP32; value: one launch per time block covering "
-                                      "all members, replayed from a hipGraph; energy_value: the same with the "
-                                      "per-step energy of every member; persistent_energy_value: one cooperative "
+                                      "all members, replayed from a hipGraph, autotuned; energy_value: the default "
+                                      "configuration with the per-step energy of every member; persistent_energy_value: one cooperative "
                                       "launch per call (grid barrier between time blocks, energies summed in the "
                                       "launch), replayed from a hipGraph; mixed_fp64_smallest4: the four smallest-eps "
                                       "members (4096^2 .. 512^2) stored in FP64, the rest FP32, one launch sequence "
@@ -837,9 +852,15 @@ def main():
         out["largest"] = {"value": round(lg["ups"], 1), "unit": "grid-point updates/s",
                           "ms_per_step": round(lg["sec"] * 1e3, 2), "time_block": lg["K"],
                           "autotuned_time_block_segment_rows_lane_columns": lg["tuned"],
+                          "autotuned_stream_policy": lg["policy"],
                           "autotune_s": round(lg["tune_s"], 2),
+                          "avg_launch_ms": round(lg["launch_ms"], 4),
+                          "kernel_GBs": round(lg["kernel_gbs"], 1),
+                          "frac": round(lg["kernel_gbs"] / 8000.0, 4),
                           "workload": "16384x16384 FP32 smooth random bathymetry 0.2-1 + delta ridge eps = 2 dx, "
-                                      "10000 steps, no energy, launch configuration from the autotuner",
+                                      "10000 steps, no energy, launch configuration (time block, rows per item, "
+                                      "lane columns, stream policy) from the autotuner; frac: algorithmic bytes "
+                                      "(5 words per node) per launch / average launch time / 8 TB/s",
                           "adjoint_crop": {"forward_ms": round(cr["forward_s"] * 1e3, 2),
                                            "adjoint_ms": round(cr["adjoint_s"] * 1e3, 2),
                                            "ratio": round(cr["ratio"], 3),

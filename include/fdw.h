@@ -250,15 +250,25 @@ enum {
     FDW_CFG_TEST_BARRIER_FLAG = 11 /* test hook: 1 marks the next fdw_step_n as if a grid barrier of the
                                       persistent launch had timed out (the host writes the error word that
                                       the call reads back; no kernel waits on it): that call returns
-                                      FDW_ESYNC; the hook then resets itself */
+                                      FDW_ESYNC; the hook then resets itself */,
+    FDW_CFG_ITEM_ORDER = 12,      /* 1 (default): every other stencil launch walks its work items in
+                                     reverse order, so the rows a launch wrote last are read first by
+                                     the next one (1-3% faster where measured); 0: one fixed order;
+                                     results are identical */
+    FDW_CFG_STREAM_POLICY = 13    /* row accesses of the forward stencil: 0 (default) non-temporal when the
+                                     working set exceeds the last-level cache; 1 non-temporal loads and
+                                     stores; 2 cacheable loads and stores; 3 non-temporal stores only;
+                                     4 non-temporal loads only (float); results are identical */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
 
 /* Autotune the execution configuration for this context (no passage: tuning): times short
  * runs of the candidate
- * (columns per lane, time block, segment rows) triples on the context's stream, picks the
- * fastest (a larger time block must win by 2%) and applies it.  Every member must be at
+ * (columns per lane, time block, segment rows) triples on the context's stream under two
+ * stream policies (automatic, and non-temporal stores with cacheable loads, where the two
+ * differ), picks the fastest (a larger time block must win by 2%) and applies it (the policy
+ * is then readable as FDW_CFG_STREAM_POLICY).  Every member must be at
  * step 0 (FDW_ESTATE otherwise) and is returned to step 0 (a checkpoint recording stops).
  * The choice is cached in the
  * file named by the FDW_AUTOTUNE_CACHE environment variable (if set) under a key of

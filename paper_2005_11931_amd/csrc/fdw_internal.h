@@ -69,8 +69,8 @@ struct StepArgs {
     int want_energy;
     int want_trace;
     int64_t ctx_step;  // context step before this launch
-    int stream_nt;     // 1: the launch's working set exceeds the last-level cache (see MemberDev)
-    int pad_;
+    int stream_nt;     // 1: non-temporal loads of the state rows (float; see MemberDev for the stores)
+    int reverse;       // 1: walk the launch's blocks in reverse order (alternating item order)
 };
 
 // Extra arguments of the persistent launch: where its energies go (as for

@@ -587,7 +587,9 @@ __device__ __forceinline__ int find_member(const MemberDev* table, int first, in
 template <typename T, int K, int C, int FACE, int MODE>
 __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step(StepArgs a)
 {
-    const int gb = xcd_remap(blockIdx.x, a.total_blocks) + a.block_offset;
+    int lb = xcd_remap(blockIdx.x, a.total_blocks);
+    if (a.reverse) lb = a.total_blocks - 1 - lb;
+    const int gb = lb + a.block_offset;
     const int m = find_member(a.table, a.first, a.nmembers, gb);
     const MemberDev& M = a.table[m];
     const int wave = (gb - M.block_base) * kWavesPerBlock + wave_in_block();

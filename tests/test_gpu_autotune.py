@@ -50,7 +50,9 @@ def test_autotune_choice_cache_and_bitwise_results(tmp_path, dtype_name):
         assert S in (8, 16, 32, 64, 128)
         assert all(s.steps_taken(m) == 0 for m in range(len(cases)))
         text = cache.read_text()
-        assert text.count("|") == 1 and text.strip().endswith(f"{K} {S} {C}")
+        P = s.config(fdw.FDW_CFG_STREAM_POLICY)
+        assert P in (0, 3)
+        assert text.count("|") == 1 and text.strip().endswith(f"{K} {S} {C} {P}")
         e = s.step(150, energy=True).cpu().numpy()
         tuned = [s.get_state(m)[0].cpu().numpy() for m in range(len(cases))]
         s.close()
@@ -137,5 +139,42 @@ def test_autotune_adjoint(tmp_path, dtype_name):
         s.close()
         tol = 1e-12 if dt == fdw.FDW_F64 else 1e-4
         assert np.abs(g - g0).max() <= tol * np.abs(g0).max()
+    finally:
+        del os.environ["FDW_AUTOTUNE_CACHE"]
+
+
+def test_autotune_stream_policy_on_a_grid_beyond_the_cache(tmp_path):
+    """A float grid whose working set exceeds the last-level cache (2 x 256 MiB): the tuner also
+    times the non-temporal-stores / cacheable-loads policy, caches its choice with the triple,
+    and a second context takes both from the cache; the tuned solve equals the default one bit
+    for bit."""
+    from paper_2005_11931_amd import fdw
+
+    n = 6144  # 5 planes x 6144^2 x 4 B = 755 MB
+    x, y, X, Y = I.mesh(n, n)
+    h = 1.0 + 0.5 * np.exp(-(X**2 + Y**2) / 0.05)
+    u0 = I.zero_ring(np.exp(-((X - 0.2) ** 2 + Y**2) / 0.01))
+    dx = 2.0 / (n - 1)
+    tau = 0.45 / np.sqrt(h.max() * 2 / dx**2)
+    case = I.Case("big", n, n, -1, 1, -1, 1, tau, 64, h, None, u0, np.zeros_like(u0))
+    cache = tmp_path / "tune.txt"
+    os.environ["FDW_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        print("autotune stream policy", flush=True)
+        s = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+        K, S, C = s.autotune(steps=16)
+        P = s.config(fdw.FDW_CFG_STREAM_POLICY)
+        assert P in (0, 3)
+        assert cache.read_text().strip().endswith(f"{K} {S} {C} {P}")
+        s.step(40)
+        tuned = s.get_state()[0].cpu().numpy()
+        s.close()
+        s2 = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+        assert s2.autotune(steps=16) == (K, S, C) and s2.config(fdw.FDW_CFG_STREAM_POLICY) == P
+        s2.close()
+        s3 = fdw.solver_for_case(case, dtype=fdw.FDW_F32)
+        s3.step(40)
+        assert np.array_equal(tuned, s3.get_state()[0].cpu().numpy())
+        s3.close()
     finally:
         del os.environ["FDW_AUTOTUNE_CACHE"]

@@ -155,6 +155,45 @@ def test_variants_bitwise(dtype_name, layout):
                     assert np.abs(E - base[2]).max() <= etol * abs(base[2][0])
 
 
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_item_order_and_stream_policy_bitwise(dtype_name):
+    """Walking every other launch's work items in reverse, and every stream policy (non-temporal
+    or cacheable loads and stores), give the same bits as the defaults: a three-member family of
+    uneven sizes, plain launches and hipGraph replay, with energies (summed in a fixed order)."""
+    import torch
+
+    fdw = _fdw()
+    dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
+    fam = I.family(count=3, nsteps=61, sizes=(67, 131, 200))
+
+    def run(order, policy, graph):
+        s = fdw.family_solver(fam, dtype=dt)
+        s.configure(fdw.FDW_CFG_ITEM_ORDER, order)
+        s.configure(fdw.FDW_CFG_STREAM_POLICY, policy)
+        s.configure(fdw.FDW_CFG_USE_GRAPH, graph)
+        assert s.config(fdw.FDW_CFG_ITEM_ORDER) == order and s.config(fdw.FDW_CFG_STREAM_POLICY) == policy
+        E = np.concatenate([s.step(k, energy=True).cpu().numpy() for k in (1, 27, 33)], axis=1)
+        st = [tuple(t.cpu().numpy() for t in s.get_state(m)[:2]) for m in range(3)]
+        s.close()
+        return st, E
+
+    base, Eb = run(0, 0, 0)
+    for order in (0, 1):
+        for policy in (0, 1, 2, 3, 4):
+            for graph in (0, 1):
+                _say("item order", order, "policy", policy, "graph", graph)
+                st, E = run(order, policy, graph)
+                for m in range(3):
+                    assert np.array_equal(st[m][0], base[m][0]) and np.array_equal(st[m][1], base[m][1]), (order, policy, m)
+                assert np.array_equal(E, Eb), (order, policy, graph)
+    with pytest.raises(fdw.FdwError):
+        s = fdw.family_solver(fam, dtype=dt)
+        try:
+            s.configure(fdw.FDW_CFG_STREAM_POLICY, 5)
+        finally:
+            s.close()
+
+
 def test_graph_replay_matches_plain():
     fdw = _fdw()
     case = I.line_case(n=200, nsteps=300)
