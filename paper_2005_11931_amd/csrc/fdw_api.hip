@@ -60,6 +60,7 @@ struct HostMember {
     int* rid = nullptr;
     double* epart = nullptr;
     int epart_stride = 0;
+    int eslots = 2;  // energy-partial slots (time blocks whose energies one finalisation sums)
     int R = 0;
     int ndup = 0;  // receivers sharing a node with an earlier one (their traces are copied)
     void* traces = nullptr;
@@ -163,6 +164,17 @@ int strips_for(int nx, int C, int K)
 // 1 column per lane and the deepest time block
 int max_strips(int nx) { return strips_for(nx, 1, kMaxTimeBlock); }
 
+// Energy-partial slots of a member: one slot holds the per-wave partials of one time block.
+// The per-time-block path fills up to this many slots before one finalisation launch sums them
+// all (fewer launches for small, launch-bound grids); at least the two the persistent launch
+// alternates, at most 64, within about 8 MiB.
+int energy_slots(const fdw_problem& p)
+{
+    const size_t maxw = (size_t)max_strips(p.nx) * (size_t)((p.ny + kMinSegRows - 1) / kMinSegRows);
+    const size_t per = sizeof(double) * kMaxTimeBlock * std::max<size_t>(maxw, 1);
+    return (int)std::max<size_t>(2, std::min<size_t>(64, ((size_t)8 << 20) / per));
+}
+
 size_t member_bytes(const fdw_problem& p)
 {
     const int ld = pitch_of(p.nx);
@@ -172,7 +184,7 @@ size_t member_bytes(const fdw_problem& p)
     b += align_up(sizeof(int) * 2 * kMaxReceivers, kAlign);        // rec_ij
     b += align_up(sizeof(int) * (size_t)(p.ny + 1), kAlign);       // rowptr
     b += 2 * align_up(sizeof(int) * kMaxReceivers, kAlign);        // col, id
-    b += align_up(sizeof(double) * 2 * kMaxTimeBlock * maxw, kAlign);  // energy partials (two slots)
+    b += align_up(sizeof(double) * (size_t)energy_slots(p) * kMaxTimeBlock * maxw, kAlign);  // energy partials
     return b;
 }
 
@@ -418,9 +430,10 @@ int do_start(fdw_ctx* c, int i, double* energy_out)
 
 // One streaming launch of K steps over members [first, first + nm) (all members when nm == count).
 template <typename T>
-int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, hipStream_t s)
+int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, hipStream_t s, int eslot = 0)
 {
     StepArgs a;
+    a.eslot = eslot;
     a.table = c->tab_dev;
     a.first = first;
     a.nmembers = nm;
@@ -481,17 +494,33 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
     const bool trace = any_trace(c);
     int64_t left = steps, k = koff;
     int curK = -1;
+    int gmax = kMaxEnergySlots;  // slots every member holds
+    for (const HostMember& hm : c->m) gmax = std::min(gmax, hm.eslots);
+    int gK = 0, gcount = 0;
+    int64_t gstart = 0;
     while (left > 0) {
         const int Kb = (int)std::min<int64_t>(std::min<int64_t>(K, left), steps_to_checkpoint(c));
+        // energies: consecutive time blocks of one length write their partials into successive
+        // slots; one finalisation sums a full group (or the group before a change of length,
+        // and the last one).  It runs before the table is laid out for a new length: the sums
+        // run over the waves of the decomposition that wrote the partials.
+        if (energy_dev && gcount > 0 && (Kb != gK || gcount == gmax)) {
+            HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, gK, energy_dev, stride, gstart,
+                                                health_word(c), s, 0, gcount));
+            gcount = 0;
+        }
         if (Kb != curK) {
             int rc = layout_for_K(c, Kb, c->S_eff, s);
             if (rc) return rc;
             curK = Kb;
         }
-        int rc = launch_block<T>(c, 0, c->count, Kb, energy_dev != nullptr, trace, s);
+        if (energy_dev && gcount == 0) {
+            gK = Kb;
+            gstart = k;
+        }
+        int rc = launch_block<T>(c, 0, c->count, Kb, energy_dev != nullptr, trace, s, energy_dev ? gcount : 0);
         if (rc) return rc;
-        if (energy_dev)
-            HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, Kb, energy_dev, stride, k, health_word(c), s));
+        if (energy_dev) ++gcount;
         c->ctx_step += Kb;
         c->launches += 1;
         for (HostMember& hm : c->m) {
@@ -503,6 +532,9 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
         left -= Kb;
         k += Kb;
     }
+    if (energy_dev && gcount > 0)
+        HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, gK, energy_dev, stride, gstart, health_word(c), s,
+                                            0, gcount));
     if (curK != K) {
         // leave the table in the main configuration
         int rc = layout_for_K(c, K, c->S_eff, s);
@@ -541,6 +573,7 @@ int run_persistent(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride
         const int ph = (int)std::min<int64_t>(kPersistentPhases, phases - done);
         HIPCHK(c, launch_fill_bytes(c->barrier, (size_t)kPersistentCtlInts * sizeof(int), s));
         StepArgs a;
+        a.eslot = 0;
         a.table = c->tab_dev;
         a.first = 0;
         a.nmembers = c->count;
@@ -877,7 +910,8 @@ int fdw_init(const fdw_problem* problems, int32_t count, void* workspace, size_t
         hm.rcol = (int*)take(sizeof(int) * kMaxReceivers);
         hm.rid = (int*)take(sizeof(int) * kMaxReceivers);
         hm.epart_stride = max_strips(p.nx) * ((p.ny + kMinSegRows - 1) / kMinSegRows);
-        hm.epart = (double*)take(sizeof(double) * 2 * kMaxTimeBlock * (size_t)hm.epart_stride);
+        hm.eslots = energy_slots(p);
+        hm.epart = (double*)take(sizeof(double) * (size_t)hm.eslots * kMaxTimeBlock * (size_t)hm.epart_stride);
 
         MemberDev& md = c->tab[i];
         std::memset(&md, 0, sizeof(md));
@@ -1492,6 +1526,7 @@ int adjoint_impl(fdw_ctx* c, int m, const int32_t* recv_ij, int R, const double*
                 pushedK = Kb;
             }
             StepArgs a;
+            a.eslot = 0;
             a.table = rep_dev;
             a.first = 0;
             a.nmembers = 1;

@@ -12,6 +12,7 @@
 namespace fdw {
 
 constexpr int kMaxTimeBlock = 8;      // time steps fused in one streaming launch
+constexpr int kMaxEnergySlots = 64;   // time blocks whose energy partials one finalisation sums
 constexpr int kWaveSize = 64;         // CDNA wavefront
 constexpr int kWavesPerBlock = 4;     // independent streaming waves per workgroup
 constexpr int kMaxReceivers = 16384;  // per member
@@ -71,6 +72,7 @@ struct StepArgs {
     int64_t ctx_step;  // context step before this launch
     int stream_nt;     // 1: non-temporal loads of the state rows (float; see MemberDev for the stores)
     int reverse;       // 1: walk the launch's blocks in reverse order (alternating item order)
+    int eslot;         // energy-partial slot the launch writes (time block within a finalisation group)
 };
 
 // Extra arguments of the persistent launch: where its energies go (as for
@@ -97,10 +99,11 @@ int persistent_max_blocks(int K, int C, int face_mode);
 template <typename T>
 // health (may be null): bit 0 set when an energy is non-finite, bit 1 when one exceeds 10x the
 // first energy of the call (energy_base[row * energy_stride], row = MemberDev::energy_row)
-// slot: which of the two partial slots holds the levels (0 except after a persistent launch)
+// slot: the partial slot holding the first time block; nslots time blocks of `levels` steps
+// each, in slots slot .. slot + nslots - 1, their energies at energy_offset + j * levels + t
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
                                   int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s,
-                                  int slot = 0);
+                                  int slot = 0, int nslots = 1);
 
 template <typename T>
 hipError_t launch_prepare_coeff(const MemberDev* m_host, const void* h1, const void* h2, int face, double* red,

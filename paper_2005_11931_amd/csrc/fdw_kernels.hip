@@ -92,15 +92,12 @@ int persistent_max_blocks<double>(int K, int C, int face_mode)
 
 // ------------------------------------------------------------------------------------------
 // Energy finalisation: E = escale * sum over waves of the per-wave partials, fixed order.
-// grid = (levels, nmembers)
+// grid = (levels, nmembers, time blocks)
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table, int first, double* energy_base,
-                                                         int64_t energy_stride, int64_t energy_offset, int* health,
-                                                         int slot)
+// Sum of one level's per-wave partials by a block of 256 (fixed order: four strided chains per
+// thread, then a tree).
+__device__ double level_partial_sum(const MemberDev& M, int slot, int t, double* red)
 {
-    const int t = blockIdx.x;
-    const int m = first + blockIdx.y;
-    const MemberDev& M = table[m];
     const double* p = M.epart + ((size_t)slot * kMaxTimeBlock + t) * M.epart_stride;
     // four independent chains so that the loads of a thread are in flight together
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -111,41 +108,57 @@ __global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table,
         for (int q = 0; q < 4; ++q) s4[q] += p[w + q * 256];
     }
     for (; w < nw; w += 256) s4[0] += p[w];
-    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-    __shared__ double red[256];
-    red[threadIdx.x] = s;
+    red[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_energy_finalize(const MemberDev* table, int first, double* energy_base,
+                                                         int64_t energy_stride, int64_t energy_offset, int* health,
+                                                         int slot)
+{
+    const int t = blockIdx.x;
+    const int m = first + blockIdx.y;
+    const int j = blockIdx.z;  // time block within the group
+    const MemberDev& M = table[m];
+    __shared__ double red[256];
+    const double E = level_partial_sum(M, slot + j, t, red) * M.escale;
+    const int64_t off = energy_offset + (int64_t)j * gridDim.x + t;
+    const int64_t row = (int64_t)M.energy_row * energy_stride;
+    // the first energy of the call, for the growth test: written by an earlier launch, or (when
+    // this group starts the call) summed here again from its partials, the same way
+    double E0 = 0.0;
+    if (health && off > 0) E0 = (energy_offset == 0) ? level_partial_sum(M, slot, 0, red) * M.escale : energy_base[row];
     if (threadIdx.x == 0) {
-        const double E = red[0] * M.escale;
-        energy_base[(int64_t)M.energy_row * energy_stride + energy_offset + t] = E;
+        energy_base[row + off] = E;
         if (health) {
             // failure detection: a non-finite energy (bit 0), or growth beyond 10x the first
-            // energy of the call (bit 1; that one was written by an earlier launch on the stream)
+            // energy of the call (bit 1)
             if (!isfinite(E)) atomicOr(health, 1);
-            if (energy_offset > 0) {
-                const double E0 = energy_base[(int64_t)M.energy_row * energy_stride];
-                if (fabs(E) > 10.0 * fabs(E0)) atomicOr(health, 2);
-            }
+            if (off > 0 && fabs(E) > 10.0 * fabs(E0)) atomicOr(health, 2);
         }
     }
 }
 
 template <typename T>
 hipError_t launch_energy_finalize(const MemberDev* table, int first, int nmembers, int levels, double* energy_base,
-                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s, int slot)
+                                  int64_t energy_stride, int64_t energy_offset, int* health, hipStream_t s, int slot,
+                                  int nslots)
 {
-    hipLaunchKernelGGL(k_energy_finalize, dim3(levels, nmembers), dim3(256), 0, s, table, first, energy_base,
+    hipLaunchKernelGGL(k_energy_finalize, dim3(levels, nmembers, nslots), dim3(256), 0, s, table, first, energy_base,
                        energy_stride, energy_offset, health, slot);
     return hipGetLastError();
 }
 template hipError_t launch_energy_finalize<float>(const MemberDev*, int, int, int, double*, int64_t, int64_t, int*,
-                                                  hipStream_t, int);
+                                                  hipStream_t, int, int);
 template hipError_t launch_energy_finalize<double>(const MemberDev*, int, int, int, double*, int64_t, int64_t, int*,
-                                                   hipStream_t, int);
+                                                   hipStream_t, int, int);
 
 // ------------------------------------------------------------------------------------------
 // Block reduction helpers (fixed order) for the generic two-stage reductions.

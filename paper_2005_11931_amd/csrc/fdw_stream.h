@@ -594,7 +594,7 @@ __global__ __launch_bounds__(kWaveSize * kWavesPerBlock) void k_step(StepArgs a)
     const MemberDev& M = a.table[m];
     const int wave = (gb - M.block_base) * kWavesPerBlock + wave_in_block();
     if (wave >= M.waves) return;
-    sweep_item<T, K, C, FACE, MODE>(M, wave, a.parity, a.ctx_step);
+    sweep_item<T, K, C, FACE, MODE>(M, wave, a.parity, a.ctx_step, a.eslot);
 }
 
 template <typename T, int K, int C, int FACE>

@@ -72,6 +72,14 @@ def test_line_fp64_parity_with_energy_and_snapshots():
         u, du = snaps[n]
         assert np.abs(u - ref["u_cur"]).max() <= 1e-12, n
         assert np.abs((u - du) - ref["u_prev"]).max() <= 1e-12, n
+    # one call of 1000 steps: the energies of up to 64 time blocks are summed by one
+    # finalisation, so a call of 250 blocks of 4 steps spans four groups (and a graph replay
+    # repeats them)
+    for K, graph in ((4, 0), (8, 1)):
+        _say("line fp64 one call, K", K, "graph", graph)
+        snaps1, E1 = _run(case, fdw.FDW_F64, 1000, K=K, energy=True, graph=graph)
+        assert np.abs(E1 - ref_e).max() <= 1e-12 * ref_e[0], K
+        assert np.array_equal(snaps1[1000][0], snaps[1000][0])
 
 
 def test_line_fp32_relative_error():
@@ -316,6 +324,46 @@ def test_traces_and_misfit_vs_oracle():
     assert np.abs(t32 - ref["traces"]).max() <= 1e-5 * np.abs(ref["traces"]).max()
     assert np.array_equal(t32[:, 4], t32[:, 5]) and np.array_equal(t32[:, 4], t32[:, 30])
     s.close()
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_trace_row_layouts_vs_oracle(dtype_name):
+    """Receivers on one grid line (with strip-edge columns and coincident receivers), on rows
+    exactly K apart, and on rows closer than K (several receiver rows in flight in one work
+    item): every layout records the oracle's traces, with time blocks 1, 3 and 8 and calls
+    that end inside a time block."""
+    import torch
+
+    fdw = _fdw()
+    dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
+    case = I.line_case(n=257, nsteps=150)
+    rng = np.random.default_rng(11)
+    j0, i0 = np.unravel_index(np.argmax(np.abs(case.u0)), case.u0.shape)
+    line = np.stack([rng.integers(1, 256, 48), np.full(48, j0)], axis=1)
+    line[:6, 0] = [1, 111, 112, 113, 224, 255]  # strip edges and the last interior column
+    line[7] = line[6] = (i0, j0)               # coincident receivers
+    layouts = {
+        "line": line,
+        "rows K apart": np.concatenate([line[:20], np.stack([line[20:, 0], np.full(28, j0 + 8)], axis=1)]),
+        "rows 3 apart": np.concatenate([line[:20], np.stack([line[20:, 0], np.full(28, j0 - 3)], axis=1)]),
+    }
+    for name, rec in layouts.items():
+        rec = rec.astype(np.int32)
+        ref = oracle.forward_case(case, receivers=rec)["traces"]
+        for K in (1, 3, 8):
+            _say("trace layout", name, "K", K, dtype_name)
+            s = fdw.solver_for_case(case, dtype=dt)
+            s.configure(fdw.FDW_CFG_TIME_BLOCK, K)
+            tr = s.record_traces(torch.as_tensor(rec))
+            s.step(37)
+            s.step(113)
+            t = tr.cpu().numpy().astype(np.float64)
+            s.close()
+            if dt == fdw.FDW_F64:
+                assert np.abs(t - ref).max() <= 1e-12, (name, K)
+            else:
+                assert np.abs(t - ref).max() <= 1e-5 * np.abs(ref).max(), (name, K)
+            assert np.array_equal(t[:, 6], t[:, 7])
 
 
 def test_energy_readout_and_resume_bitwise():
