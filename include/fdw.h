@@ -302,11 +302,12 @@ int fdw_kernel_time(fdw_ctx* ctx, double* ms, int64_t* launches);
  *     (I - sigma tau^2 L1)(I - sigma tau^2 L2)(u^{n+1} - 2u^n + u^{n-1}) = tau^2 (L1 + L2) u^n,
  * L1 = d_x(h1 d_x .), L2 = d_y(h2 d_y .) with the face coefficients and zero Dirichlet data of the
  * explicit solver, start u^1 = u^0 + tau u1 + w^0/2 (w^0 the same solve applied to tau^2 A u^0);
- * every factor is a set of tridiagonal systems, one per grid line, solved by cyclic reduction
- * in LDS.  sigma >= 1/4 is unconditionally stable (constant coefficients: every mode); sigma = 0
- * is the leapfrog scheme.  The state is carried as (u, du = u^n - u^{n-1}).  Limits: the padded
- * line length 2^p - 1 >= max(nx, ny) - 2 must fit four arrays in LDS (nx, ny <= 4097 in FP64,
- * 8193 in FP32 on gfx950; FDW_ENOTSUP beyond). */
+ * every factor is a set of tridiagonal systems, one per grid line, each solved by one workgroup:
+ * elimination within contiguous chunks of the line, then cyclic reduction in LDS on the system of
+ * the chunks' interface unknowns.  sigma >= 1/4 is unconditionally stable (constant coefficients:
+ * every mode); sigma = 0 is the leapfrog scheme.  The state is carried as (u, du = u^n - u^{n-1}).
+ * Limits: max(nx, ny) - 2 <= 4352 in FP64, 8448 in FP32 (256 chunks of at most 17 / 33 unknowns
+ * per line; FDW_ENOTSUP beyond). */
 typedef struct fdw_adi fdw_adi; /* opaque */
 
 /* Device workspace (bytes) of one implicit solver for problem p (0 if p is invalid). */

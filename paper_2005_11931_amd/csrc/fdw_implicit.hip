@@ -7,9 +7,11 @@
 //     (I - s tau^2 L1)(I - s tau^2 L2) w^n = tau^2 (L1 + L2) u^n,
 //     du^{n+1} = du^n + w^n,  u^{n+1} = u^n + du^{n+1}    (i.e. u^{n+1} - 2u^n + u^{n-1} = w^n),
 // start du^1 = tau u1 + w^0 / 2.  One step is four kernels:
-//   1. x lines: the right-hand side tau^2 A u is formed from three rows of u, the row's tridiagonal
-//      system (I - s tau^2 L1) z = r is built in LDS and solved there by cyclic reduction; one
-//      workgroup per grid row;
+//   1. x lines: the right-hand side tau^2 A u is formed from three rows of u and the row's
+//      tridiagonal system (I - s tau^2 L1) z = r is solved, one workgroup per grid row: each
+//      thread eliminates within a contiguous chunk of the line (in registers), which leaves two
+//      interface unknowns per chunk coupled in a tridiagonal system of their own; that one is
+//      solved by cyclic reduction in LDS, and each thread then recovers its chunk's interior;
 //   2. z is transposed (64 x 64 LDS tiles) so that the y lines are contiguous;
 //   3. y lines: the same cyclic-reduction solve on the rows of z^T with the transposed y faces;
 //   4. w^T is transposed back through LDS tiles and added into (du, u).
@@ -28,7 +30,13 @@
 
 namespace {
 
-constexpr int kLineThreads = 512;  // threads of a line-solve workgroup
+constexpr int kLineThreads = 256;            // threads of a line-solve workgroup (one chunk each)
+constexpr int kReducedPad = 1023;            // 2^10 - 1 >= the 2 x 256 interface unknowns
+template <typename T>
+constexpr int line_chunk() { return sizeof(T) == 8 ? 17 : 33; }  // most unknowns per thread
+// longest line (interior unknowns) one workgroup solves
+template <typename T>
+constexpr int max_line_unknowns() { return kLineThreads * line_chunk<T>(); }
 constexpr int kTile = 64;          // transpose tile
 constexpr size_t kAdiAlign = 256;
 inline size_t adi_align(size_t v) { return (v + kAdiAlign - 1) / kAdiAlign * kAdiAlign; }
@@ -78,7 +86,6 @@ struct LineArgs {
     int lines;      // number of lines (rows of the source layout)
     int len;        // nodes per line (including the two boundary nodes)
     int ld;         // pitch of the line layout (elements)
-    int M;          // padded system size 2^p - 1 >= len - 2
     double g;       // s tau^2 / d^2 along the line
     const void* F;  // face coefficients along the line: F[line][i] between nodes i and i+1
     void* out;      // solution, [lines][ld]
@@ -86,62 +93,220 @@ struct LineArgs {
     const void* u;
     const void* hx;
     const void* hy;
-    double dx2, dy2;  // dx^2, dy^2
+    double idx2, idy2;  // 1 / dx^2, 1 / dy^2
     double tt;      // tau^2
     const void* rhs;  // !FROM_U: right-hand side rows [lines][ld]
 };
 
-template <typename T, bool FROM_U>
+// LDS index of element k of a staged line: one pad slot per chunk of MT elements, so that
+// threads reading the elements of their own chunks spread over the banks
+template <int MT>
+__device__ __host__ constexpr int lds_pad(int k)
+{
+    return k + k / MT;
+}
+
+// Chunk length (unknowns per thread) for lines of n unknowns: the shortest of 5, 9, 17, 33 that
+// covers the line with 256 threads.  The odd lengths keep the number of interface unknowns of
+// lines of 2^k - 2 unknowns (grids of 2^k nodes) below a power of two, so that the padded
+// interface system is not twice as large as needed.
+template <typename T>
+int line_chunk_for(int n)
+{
+    int mt = 5;
+    while (mt < line_chunk<T>() && kLineThreads * mt < n) mt = 2 * mt - 1;
+    return mt;
+}
+
+// LDS (elements) of a line workgroup: in turn the staged right-hand sides and faces of P chunks
+// of MT unknowns, the interface system (four arrays of 2^q - 1 >= 2P), and the staged solution
+inline int line_lds_elems(int n, int MT, bool from_u)
+{
+    const int P = std::max(1, (n + MT - 1) / MT);
+    int M = 1;
+    while (M < 2 * P) M = 2 * M + 1;
+    const int span = P * MT;  // right-hand sides d_0 .. d_{P MT - 1}
+    return std::max(span + span / MT + 2, 4 * M);
+}
+
+// One line system per workgroup: a_k z_{k-1} + b_k z_k + c_k z_{k+1} = d_k, k = 0..n-1 (unknowns at
+// the interior nodes i = k + 1), a_k = -g F_{i-1}, c_k = -g F_i, b_k = 1 + g (F_{i-1} + F_i).
+// Partition method: the unknowns are split into P = ceil(n / MT) chunks of MT, one per thread,
+// the last one padded with identity rows (decoupled: c_{n-1} = 0).  Each thread loads its chunk's
+// faces and right-hand sides (the x lines form the right-hand side from u first, with coalesced
+// loads staged through LDS).  In chunk [lo, lo + MT) a downward sweep over rows lo+1 .., with
+// z_lo kept as a parameter, gives z_k = d'_k - a'_k z_lo - c'_k z_{k+1}; an upward sweep then
+// gives z_k = d~_k - a~_k z_lo - c~_k z_hi (hi = lo + MT - 1) for lo < k < hi.  Row lo (with
+// z_{lo+1} substituted) and the last row of the downward sweep couple (z_lo, z_hi) of
+// neighbouring chunks in a tridiagonal system of 2P unknowns, solved by cyclic reduction in LDS;
+// the interior follows.  Eliminations without pivoting are safe: the systems are strictly
+// diagonally dominant.
+template <typename T, int MT, bool FROM_U>
 __global__ __launch_bounds__(kLineThreads) void k_adi_lines(LineArgs A)
 {
+    static_assert(MT >= 4, "chunks of at least four unknowns");
     extern __shared__ unsigned char smem[];
-    T* a = reinterpret_cast<T*>(smem);
-    T* b = a + A.M;
-    T* c = b + A.M;
-    T* d = c + A.M;
+    T* const sD = reinterpret_cast<T*>(smem);
     const int line = blockIdx.x;
     const int n = A.len - 2;
     const int ld = A.ld;
+    const int P = max(1, (n + MT - 1) / MT);
     T* out = (T*)A.out + (size_t)line * ld;
-    if (line == 0 || line == A.lines - 1) {  // boundary lines: zero
+    if (line == 0 || line == A.lines - 1) {  // boundary lines: zero (the whole block returns)
         for (int i = threadIdx.x; i < A.len; i += blockDim.x) out[i] = T(0);
         return;
     }
-    const T* F = (const T*)A.F + (size_t)line * ld;
     const T g = (T)A.g;
-    for (int k = threadIdx.x; k < A.M; k += blockDim.x) {
-        if (k < n) {
-            const int i = k + 1;
-            const T fl = F[i - 1], fr = F[i];
-            a[k] = (k > 0) ? -g * fl : T(0);
-            c[k] = (k < n - 1) ? -g * fr : T(0);
-            b[k] = T(1) + g * (fl + fr);
-            T r;
-            if constexpr (FROM_U) {
-                // tau^2 (A u)_{line, i}: flux form, opposite faces added as pairs (as the explicit
-                // solver and the oracle form it)
-                const T* u = (const T*)A.u + (size_t)line * ld;
-                const T* hx = (const T*)A.hx + (size_t)line * ld;
-                const T* hy = (const T*)A.hy + (size_t)line * ld;
+    const int span = P * MT;  // unknowns of the padded line
+    // ---- the line's faces F_0 .. F_span and right-hand sides d_0 .. d_{span-1} (zero past the
+    // line) are read with coalesced loads and passed through LDS to the threads whose chunks
+    // hold them; every thread has at most MT + 1 elements of each.  Loads past the line read the
+    // last element instead and their values are replaced by zero afterwards: no branch around a
+    // load, so that the loads of one thread are in flight together
+    constexpr int NQ = MT + 1;
+    T fq[NQ];
+    {
+        const T* F = (const T*)A.F + (size_t)line * ld;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int i = (int)threadIdx.x + q * kLineThreads;
+            const T f = F[min(i, n)];
+            fq[q] = (i <= n) ? f : T(0);
+        }
+    }
+    if constexpr (FROM_U) {
+        // tau^2 (A u)_{line, i} in flux form, opposite faces added as pairs (as the explicit
+        // solver and the oracle form it; the scalings by 1/dx^2 and 1/dy^2 are products with the
+        // reciprocals, which differ from the quotients by rounding only); the loads of six nodes
+        // per thread are issued together
+        const T* u = (const T*)A.u + (size_t)line * ld;
+        const T* hx = (const T*)A.hx + (size_t)line * ld;
+        const T* hy = (const T*)A.hy + (size_t)line * ld;
+        const T idx2 = (T)A.idx2, idy2 = (T)A.idy2, tt = (T)A.tt;
+        constexpr int kBatch = 6;
+#pragma unroll
+        for (int q0 = 0; q0 < MT; q0 += kBatch) {
+            T dv[kBatch];
+#pragma unroll
+            for (int q = q0; q < q0 + kBatch; ++q) {
+                const int iq = 1 + (int)threadIdx.x + q * kLineThreads;
+                const int i = min(iq, n);
                 const T uc = u[i];
                 const T east = hx[i] * (u[i + 1] - uc);
                 const T west = hx[i - 1] * (u[i - 1] - uc);
                 const T north = hy[i] * (u[i + ld] - uc);
                 const T south = hy[i - ld] * (u[i - ld] - uc);
-                r = ((east + west) / (T)A.dx2 + (north + south) / (T)A.dy2) * (T)A.tt;
-            } else {
-                r = ((const T*)A.rhs)[(size_t)line * ld + i];
+                const T d = ((east + west) * idx2 + (north + south) * idy2) * tt;
+                dv[q - q0] = (iq <= n) ? d : T(0);
             }
-            d[k] = r;
-        } else {
-            a[k] = T(0);
-            c[k] = T(0);
-            b[k] = T(1);
-            d[k] = T(0);
+#pragma unroll
+            for (int q = q0; q < q0 + kBatch; ++q) {
+                const int k = (int)threadIdx.x + q * kLineThreads;
+                if (k < span) sD[lds_pad<MT>(k)] = dv[q - q0];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        const T* r = (const T*)A.rhs + (size_t)line * ld;
+        T dq[MT];
+#pragma unroll
+        for (int q = 0; q < MT; ++q) {
+            const int i = 1 + (int)threadIdx.x + q * kLineThreads;
+            const T d = r[min(i, n)];
+            dq[q] = (i <= n) ? d : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < MT; ++q) {
+            const int k = (int)threadIdx.x + q * kLineThreads;
+            if (k < span) sD[lds_pad<MT>(k)] = dq[q];
         }
     }
-    cyclic_reduction<T>(a, b, c, d, A.M);
-    for (int i = threadIdx.x; i < A.len; i += blockDim.x) out[i] = (i >= 1 && i <= n) ? d[i - 1] : T(0);
+    __syncthreads();
+    const int p = threadIdx.x;
+    const bool act = p < P;
+    const int lo = p * MT;
+    T fv[MT + 1], dv[MT];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) dv[q] = act ? sD[lds_pad<MT>(lo + q)] : T(0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = (int)threadIdx.x + q * kLineThreads;
+        if (i <= span) sD[lds_pad<MT>(i)] = fq[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q <= MT; ++q) fv[q] = act ? sD[lds_pad<MT>(lo + q)] : T(0);
+    // row j of the chunk (identity rows past the line)
+    auto row = [&](int j, T& a, T& b, T& c, T& d) {
+        const int k = lo + j;
+        const T fl = fv[j], fr = fv[j + 1];
+        const bool real = k < n;
+        a = (k > 0 && real) ? -g * fl : T(0);
+        c = (k < n - 1) ? -g * fr : T(0);
+        b = real ? T(1) + g * (fl + fr) : T(1);
+        d = dv[j];
+    };
+    T ap[MT], cp[MT], dp[MT];
+    T a0, b0, c0, d0;
+    row(0, a0, b0, c0, d0);
+    // downward sweep over rows lo+1 .. hi
+    {
+        T a, b, c, d;
+        row(1, a, b, c, d);
+        const T rr = T(1) / b;
+        ap[1] = a * rr;
+        cp[1] = c * rr;
+        dp[1] = d * rr;
+    }
+#pragma unroll
+    for (int j = 2; j < MT; ++j) {
+        T a, b, c, d;
+        row(j, a, b, c, d);
+        const T rr = T(1) / (b - a * cp[j - 1]);
+        cp[j] = c * rr;
+        dp[j] = (d - a * dp[j - 1]) * rr;
+        ap[j] = -(a * ap[j - 1]) * rr;
+    }
+    const T ha = ap[MT - 1], hc = cp[MT - 1], hr = dp[MT - 1];
+    // upward sweep: rows hi-2 .. lo+1 in terms of z_lo and z_hi
+#pragma unroll
+    for (int j = MT - 3; j >= 1; --j) {
+        const T q = cp[j];
+        dp[j] = dp[j] - q * dp[j + 1];
+        ap[j] = ap[j] - q * ap[j + 1];
+        cp[j] = -(q * cp[j + 1]);
+    }
+    const T la = a0, lb = b0 - c0 * ap[1], lc = -(c0 * cp[1]), lr = d0 - c0 * dp[1];
+    // interface system in the same LDS (once every thread has read its rows): unknowns
+    // (z_lo, z_hi) of chunk p at 2p, 2p+1, padded with identity rows to 2^q - 1
+    int M = 1;
+    while (M < 2 * P) M = 2 * M + 1;
+    T* const ra = sD;
+    T* const rb = ra + M;
+    T* const rc = rb + M;
+    T* const rd = rc + M;
+    __syncthreads();
+    if (act) {
+        ra[2 * p] = la, rb[2 * p] = lb, rc[2 * p] = lc, rd[2 * p] = lr;
+        ra[2 * p + 1] = ha, rb[2 * p + 1] = T(1), rc[2 * p + 1] = hc, rd[2 * p + 1] = hr;
+    }
+    for (int k = 2 * P + threadIdx.x; k < M; k += blockDim.x) ra[k] = T(0), rb[k] = T(1), rc[k] = T(0), rd[k] = T(0);
+    cyclic_reduction<T>(ra, rb, rc, rd, M);
+    // the chunk's solution, staged in LDS (over the interface system, once every thread has read
+    // its two values) and stored with coalesced writes
+    T xl = T(0), xh = T(0);
+    if (act) xl = rd[2 * p], xh = rd[2 * p + 1];
+    __syncthreads();
+    T* const sX = sD;
+    if (act) {
+        sX[lds_pad<MT>(lo)] = xl;
+#pragma unroll
+        for (int j = 1; j < MT - 1; ++j) sX[lds_pad<MT>(lo + j)] = dp[j] - ap[j] * xl - cp[j] * xh;
+        sX[lds_pad<MT>(lo + MT - 1)] = xh;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < A.len; i += blockDim.x) out[i] = (i >= 1 && i <= n) ? sX[lds_pad<MT>(i - 1)] : T(0);
 }
 
 // out[c][r] = in[r][c] for r < rows, c < cols (pitches ld_in, ld_out), through 64 x 64 LDS tiles.
@@ -254,19 +419,11 @@ __global__ void k_adi_copy_out(const T* __restrict__ src, int nx, int ny, int ld
         dst[k] = src[(size_t)(k / nx) * ld + (k % nx)];
 }
 
-int pow2_minus1_at_least(int n)
-{
-    int M = 1;
-    while (M < n) M = 2 * M + 1;
-    return M;
-}
-
 }  // namespace
 
 struct fdw_adi {
     fdw_problem p;
     int nx = 0, ny = 0, ld = 0, ldT = 0;
-    int Mx = 0, My = 0;
     int64_t N = 0, n = 0;
     double dx = 0, dy = 0, sigma = 0.25;
     hipStream_t stream = nullptr;
@@ -294,8 +451,42 @@ int adi_fail(fdw_adi* s, int code, const std::string& msg)
         if (e_ != hipSuccess) return adi_fail((s), FDW_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+template <typename T, int MT>
+bool allow_lds_mt(int bytes)
+{
+    return hipFuncSetAttribute((const void*)k_adi_lines<T, MT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               bytes) == hipSuccess &&
+           hipFuncSetAttribute((const void*)k_adi_lines<T, MT, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               bytes) == hipSuccess;
+}
+
+// let the line kernel that lines of up to n unknowns use take the LDS it needs
 template <typename T>
-hipError_t launch_lines(const fdw_adi* s, bool from_u, const void* F, int lines, int len, int ld, int M, double g,
+int allow_line_lds(int n)
+{
+    const int mt = line_chunk_for<T>(n);
+    const int bytes = line_lds_elems(n, mt, true) * (int)sizeof(T);
+    bool ok = true;
+    switch (mt) {
+    case 5: ok = allow_lds_mt<T, 5>(bytes); break;
+    case 9: ok = allow_lds_mt<T, 9>(bytes); break;
+    case 17: ok = allow_lds_mt<T, 17>(bytes); break;
+    default: ok = allow_lds_mt<T, line_chunk<T>()>(bytes); break;
+    }
+    return ok ? FDW_OK : FDW_EHIP;
+}
+
+template <typename T, int MT>
+void launch_lines_mt(bool from_u, dim3 gr, dim3 bl, size_t shmem, hipStream_t st, const LineArgs& A)
+{
+    if (from_u)
+        hipLaunchKernelGGL((k_adi_lines<T, MT, true>), gr, bl, shmem, st, A);
+    else
+        hipLaunchKernelGGL((k_adi_lines<T, MT, false>), gr, bl, shmem, st, A);
+}
+
+template <typename T>
+hipError_t launch_lines(const fdw_adi* s, bool from_u, const void* F, int lines, int len, int ld, double g,
                         const void* rhs, void* out)
 {
     LineArgs A;
@@ -303,22 +494,25 @@ hipError_t launch_lines(const fdw_adi* s, bool from_u, const void* F, int lines,
     A.lines = lines;
     A.len = len;
     A.ld = ld;
-    A.M = M;
     A.g = g;
     A.F = F;
     A.out = out;
     A.u = (s->n == 0) ? s->u0 : s->u;  // the start step solves with the initial displacement
     A.hx = s->hx;
     A.hy = s->hy;
-    A.dx2 = s->dx * s->dx;
-    A.dy2 = s->dy * s->dy;
+    A.idx2 = 1.0 / (s->dx * s->dx);
+    A.idy2 = 1.0 / (s->dy * s->dy);
     A.tt = s->p.tau * s->p.tau;
     A.rhs = rhs;
-    const size_t shmem = 4 * (size_t)M * sizeof(T);
-    if (from_u)
-        hipLaunchKernelGGL((k_adi_lines<T, true>), dim3(lines), dim3(kLineThreads), shmem, s->stream, A);
-    else
-        hipLaunchKernelGGL((k_adi_lines<T, false>), dim3(lines), dim3(kLineThreads), shmem, s->stream, A);
+    const int mt = line_chunk_for<T>(len - 2);
+    const size_t shmem = (size_t)line_lds_elems(len - 2, mt, from_u) * sizeof(T);
+    const dim3 gr(lines), bl(kLineThreads);
+    switch (mt) {
+    case 5: launch_lines_mt<T, 5>(from_u, gr, bl, shmem, s->stream, A); break;
+    case 9: launch_lines_mt<T, 9>(from_u, gr, bl, shmem, s->stream, A); break;
+    case 17: launch_lines_mt<T, 17>(from_u, gr, bl, shmem, s->stream, A); break;
+    default: launch_lines_mt<T, line_chunk<T>()>(from_u, gr, bl, shmem, s->stream, A); break;
+    }
     return hipGetLastError();
 }
 
@@ -328,15 +522,14 @@ int adi_step(fdw_adi* s, bool start)
 {
     const double tt = s->p.tau * s->p.tau;
     // x lines: rows of the normal layout
-    ADICHK(s, launch_lines<T>(s, true, s->hx, s->ny, s->nx, s->ld, s->Mx, s->sigma * tt / (s->dx * s->dx), nullptr,
-                              s->z));
+    ADICHK(s, launch_lines<T>(s, true, s->hx, s->ny, s->nx, s->ld, s->sigma * tt / (s->dx * s->dx), nullptr, s->z));
     // z -> z^T
     const dim3 tg((s->nx + kTile - 1) / kTile, (s->ny + kTile - 1) / kTile);
     hipLaunchKernelGGL((k_transpose<T>), tg, dim3(256), 0, s->stream, (const T*)s->z, s->ny, s->nx, s->ld, (T*)s->zT,
                        s->ldT);
     ADICHK(s, hipGetLastError());
     // y lines: rows of the transposed layout
-    ADICHK(s, launch_lines<T>(s, false, s->hyT, s->nx, s->ny, s->ldT, s->My, s->sigma * tt / (s->dy * s->dy), s->zT,
+    ADICHK(s, launch_lines<T>(s, false, s->hyT, s->nx, s->ny, s->ldT, s->sigma * tt / (s->dy * s->dy), s->zT,
                               s->wT));
     // w^T -> (du, u)
     const dim3 ug((s->nx + kTile - 1) / kTile, (s->ny + kTile - 1) / kTile);
@@ -427,17 +620,9 @@ int fdw_adi_init(const fdw_problem* p, double sigma, void* workspace, size_t ws_
     s->dy = (p->y1 - p->y0) / (p->ny - 1);
     s->sigma = sigma;
     s->stream = (hipStream_t)hip_stream;
-    s->Mx = pow2_minus1_at_least(p->nx - 2);
-    s->My = pow2_minus1_at_least(p->ny - 2);
-    // the line systems live in LDS: 4 arrays of the padded size
-    int dev = 0, lds = 0;
-    const size_t es = p->dtype == FDW_F32 ? 4 : 8;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
-        delete s;
-        return FDW_EHIP;
-    }
-    if (4 * (size_t)std::max(s->Mx, s->My) * es > (size_t)lds) {
+    // a line of n unknowns is solved by one workgroup: n <= 256 chunks of line_chunk<T>() unknowns
+    const int maxn = (p->dtype == FDW_F32) ? max_line_unknowns<float>() : max_line_unknowns<double>();
+    if (std::max(p->nx, p->ny) - 2 > maxn) {
         delete s;
         return FDW_ENOTSUP;
     }
@@ -465,23 +650,13 @@ int fdw_adi_init(const fdw_problem* p, double sigma, void* workspace, size_t ws_
         delete s;
         return FDW_EHIP;
     }
-    const size_t lds_x = 4 * (size_t)s->Mx * es, lds_y = 4 * (size_t)s->My * es;
-    // allow the line kernels the dynamic LDS they need (a request the device cannot grant shows
-    // as a launch error on the first step)
-    hipError_t ea, eb;
-    if (p->dtype == FDW_F32) {
-        ea = hipFuncSetAttribute((const void*)k_adi_lines<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_x);
-        eb = hipFuncSetAttribute((const void*)k_adi_lines<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_y);
-    } else {
-        ea = hipFuncSetAttribute((const void*)k_adi_lines<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_x);
-        eb = hipFuncSetAttribute((const void*)k_adi_lines<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds_y);
+    // the line kernels' dynamic LDS (above the default limit for the longest lines)
+    const int rc0 = (p->dtype == FDW_F32) ? allow_line_lds<float>(std::max(p->nx, p->ny) - 2)
+                                          : allow_line_lds<double>(std::max(p->nx, p->ny) - 2);
+    if (rc0 != FDW_OK) {
+        delete s;
+        return rc0;
     }
-    (void)ea;
-    (void)eb;
     const int rc = (p->dtype == FDW_F32) ? adi_setup<float>(s, u0, u1, h1, h2) : adi_setup<double>(s, u0, u1, h1, h2);
     if (rc) {
         const int code = rc;

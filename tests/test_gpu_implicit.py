@@ -33,11 +33,13 @@ def _variable_case(nx, ny, N, cfl):
     return I.Case("adi", nx, ny, -1, 1, -1, 1, tau, N, h1, h2, u0, u1)
 
 
-@pytest.mark.parametrize("nx,ny", [(3, 3), (37, 53), (257, 131), (5, 700), (1030, 66), (513, 513)])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (4, 6), (37, 53), (257, 131), (5, 700), (1030, 66), (513, 513),
+                                   (2100, 9), (4098, 7), (4354, 5)])
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
 def test_adi_vs_oracle(nx, ny, dtype_name):
-    """Ragged sizes (line lengths around powers of two, single unknowns, long thin grids),
-    h1 != h2 varying in x and y, a step 3x the explicit limit."""
+    """Ragged sizes (line lengths around powers of two, single unknowns, long thin grids, lines
+    that take every chunk length of the line solver up to the longest FP64 line), h1 != h2
+    varying in x and y, a step 3x the explicit limit."""
     from paper_2005_11931_amd import fdw
 
     dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
@@ -58,6 +60,22 @@ def test_adi_vs_oracle(nx, ny, dtype_name):
         assert np.abs(du - (ref["u_cur"] - ref["u_prev"])).max() <= 1e-12 * amp
     else:
         assert np.abs(u - ref["u_cur"]).max() <= 1e-5 * max(np.abs(ref["u_cur"]).max(), 1e-300)
+
+
+@pytest.mark.parametrize("nx,ny", [(6000, 5), (8450, 4)])
+def test_adi_fp32_longest_lines_vs_oracle(nx, ny):
+    """FP32 lines longer than the FP64 limit (33 unknowns per thread; 8448 unknowns is the
+    longest line one workgroup solves)."""
+    from paper_2005_11931_amd import fdw
+
+    case = _variable_case(nx, ny, 40, cfl=3.0)
+    _say("adi fp32", nx, ny)
+    s = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=fdw.FDW_F32)
+    s.step(40)
+    u = s.get_state()[0].cpu().numpy().astype(np.float64)
+    s.close()
+    ref = oracle.adi_forward_case(case, sigma=0.25)["u_cur"]
+    assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
 def test_adi_sigma_zero_is_the_leapfrog_scheme():
