@@ -330,8 +330,10 @@ def test_traces_and_misfit_vs_oracle():
 def test_trace_row_layouts_vs_oracle(dtype_name):
     """Receivers on one grid line (with strip-edge columns and coincident receivers), on rows
     exactly K apart, and on rows closer than K (several receiver rows in flight in one work
-    item): every layout records the oracle's traces, with time blocks 1, 3 and 8 and calls
-    that end inside a time block."""
+    item, six adjacent receiver rows): every layout records the oracle's traces, with time
+    blocks 1, 3 and 8, work items of automatic length, 64 rows (receivers looked up once per
+    item, the first four receiver rows ahead of the row stream) and 256 rows (searched row by
+    row), and calls that end inside a time block."""
     import torch
 
     fdw = _fdw()
@@ -346,24 +348,31 @@ def test_trace_row_layouts_vs_oracle(dtype_name):
         "line": line,
         "rows K apart": np.concatenate([line[:20], np.stack([line[20:, 0], np.full(28, j0 + 8)], axis=1)]),
         "rows 3 apart": np.concatenate([line[:20], np.stack([line[20:, 0], np.full(28, j0 - 3)], axis=1)]),
+        # six adjacent receiver rows: more receiver rows in one work item than it looks up
+        # ahead of its row stream (the rest are searched row by row)
+        "six rows": np.stack([line[:, 0], j0 - 2 + np.arange(48) % 6], axis=1),
     }
     for name, rec in layouts.items():
         rec = rec.astype(np.int32)
         ref = oracle.forward_case(case, receivers=rec)["traces"]
-        for K in (1, 3, 8):
-            _say("trace layout", name, "K", K, dtype_name)
+        # rows per work item: automatic, 64 (looked up per item) and 256 (searched per row)
+        for K, S in ((1, 0), (3, 64), (8, 0), (8, 64), (8, 256)):
+            _say("trace layout", name, "K", K, "S", S, dtype_name)
             s = fdw.solver_for_case(case, dtype=dt)
             s.configure(fdw.FDW_CFG_TIME_BLOCK, K)
+            if S:
+                s.configure(fdw.FDW_CFG_SEGMENT_ROWS, S)
             tr = s.record_traces(torch.as_tensor(rec))
             s.step(37)
             s.step(113)
             t = tr.cpu().numpy().astype(np.float64)
             s.close()
             if dt == fdw.FDW_F64:
-                assert np.abs(t - ref).max() <= 1e-12, (name, K)
+                assert np.abs(t - ref).max() <= 1e-12, (name, K, S)
             else:
-                assert np.abs(t - ref).max() <= 1e-5 * np.abs(ref).max(), (name, K)
-            assert np.array_equal(t[:, 6], t[:, 7])
+                assert np.abs(t - ref).max() <= 1e-5 * np.abs(ref).max(), (name, K, S)
+            if name != "six rows":
+                assert np.array_equal(t[:, 6], t[:, 7])
 
 
 def test_energy_readout_and_resume_bitwise():
