@@ -431,6 +431,11 @@ struct fdw_adi {
     void *u = nullptr, *du = nullptr, *u0 = nullptr, *u1 = nullptr, *hx = nullptr, *hy = nullptr, *hyT = nullptr;
     void *z = nullptr, *zT = nullptr, *wT = nullptr;
     double* red = nullptr;
+    // kAdiGraphSteps steps (after the start step) captured once in a hipGraph on a private
+    // stream and replayed on `stream`
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_failed = false;
 };
 
 namespace {
@@ -487,7 +492,7 @@ void launch_lines_mt(bool from_u, dim3 gr, dim3 bl, size_t shmem, hipStream_t st
 
 template <typename T>
 hipError_t launch_lines(const fdw_adi* s, bool from_u, const void* F, int lines, int len, int ld, double g,
-                        const void* rhs, void* out)
+                        const void* rhs, void* out, hipStream_t st)
 {
     LineArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -508,39 +513,65 @@ hipError_t launch_lines(const fdw_adi* s, bool from_u, const void* F, int lines,
     const size_t shmem = (size_t)line_lds_elems(len - 2, mt, from_u) * sizeof(T);
     const dim3 gr(lines), bl(kLineThreads);
     switch (mt) {
-    case 5: launch_lines_mt<T, 5>(from_u, gr, bl, shmem, s->stream, A); break;
-    case 9: launch_lines_mt<T, 9>(from_u, gr, bl, shmem, s->stream, A); break;
-    case 17: launch_lines_mt<T, 17>(from_u, gr, bl, shmem, s->stream, A); break;
-    default: launch_lines_mt<T, line_chunk<T>()>(from_u, gr, bl, shmem, s->stream, A); break;
+    case 5: launch_lines_mt<T, 5>(from_u, gr, bl, shmem, st, A); break;
+    case 9: launch_lines_mt<T, 9>(from_u, gr, bl, shmem, st, A); break;
+    case 17: launch_lines_mt<T, 17>(from_u, gr, bl, shmem, st, A); break;
+    default: launch_lines_mt<T, line_chunk<T>()>(from_u, gr, bl, shmem, st, A); break;
     }
     return hipGetLastError();
 }
 
-// one solve w = B^{-1} tau^2 A u (into wT, transposed) and the update of (du, u)
+// one solve w = B^{-1} tau^2 A u (into wT, transposed) and the update of (du, u), on stream st
 template <typename T>
-int adi_step(fdw_adi* s, bool start)
+int adi_step(fdw_adi* s, bool start, hipStream_t st)
 {
     const double tt = s->p.tau * s->p.tau;
     // x lines: rows of the normal layout
-    ADICHK(s, launch_lines<T>(s, true, s->hx, s->ny, s->nx, s->ld, s->sigma * tt / (s->dx * s->dx), nullptr, s->z));
+    ADICHK(s, launch_lines<T>(s, true, s->hx, s->ny, s->nx, s->ld, s->sigma * tt / (s->dx * s->dx), nullptr, s->z, st));
     // z -> z^T
     const dim3 tg((s->nx + kTile - 1) / kTile, (s->ny + kTile - 1) / kTile);
-    hipLaunchKernelGGL((k_transpose<T>), tg, dim3(256), 0, s->stream, (const T*)s->z, s->ny, s->nx, s->ld, (T*)s->zT,
-                       s->ldT);
+    hipLaunchKernelGGL((k_transpose<T>), tg, dim3(256), 0, st, (const T*)s->z, s->ny, s->nx, s->ld, (T*)s->zT, s->ldT);
     ADICHK(s, hipGetLastError());
     // y lines: rows of the transposed layout
     ADICHK(s, launch_lines<T>(s, false, s->hyT, s->nx, s->ny, s->ldT, s->sigma * tt / (s->dy * s->dy), s->zT,
-                              s->wT));
+                              s->wT, st));
     // w^T -> (du, u)
     const dim3 ug((s->nx + kTile - 1) / kTile, (s->ny + kTile - 1) / kTile);
     if (start)
-        hipLaunchKernelGGL((k_adi_update<T, true>), ug, dim3(256), 0, s->stream, (const T*)s->wT, s->ldT, s->nx, s->ny,
+        hipLaunchKernelGGL((k_adi_update<T, true>), ug, dim3(256), 0, st, (const T*)s->wT, s->ldT, s->nx, s->ny,
                            s->ld, (T*)s->du, (T*)s->u, (const T*)s->u0, (const T*)s->u1, (T)s->p.tau);
     else
-        hipLaunchKernelGGL((k_adi_update<T, false>), ug, dim3(256), 0, s->stream, (const T*)s->wT, s->ldT, s->nx,
-                           s->ny, s->ld, (T*)s->du, (T*)s->u, (const T*)s->u0, (const T*)s->u1, (T)s->p.tau);
+        hipLaunchKernelGGL((k_adi_update<T, false>), ug, dim3(256), 0, st, (const T*)s->wT, s->ldT, s->nx, s->ny,
+                           s->ld, (T*)s->du, (T*)s->u, (const T*)s->u0, (const T*)s->u1, (T)s->p.tau);
     ADICHK(s, hipGetLastError());
     return FDW_OK;
+}
+
+constexpr int kAdiGraphSteps = 16;
+
+// capture kAdiGraphSteps ordinary steps once (their launches depend on nothing but the solver's
+// fixed buffers); on any failure the solver keeps launching step by step
+template <typename T>
+void adi_capture(fdw_adi* s)
+{
+    if (!s->cap && hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) {
+        s->cap = nullptr;
+        s->graph_failed = true;
+        return;
+    }
+    if (hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        s->graph_failed = true;
+        return;
+    }
+    int rc = FDW_OK;
+    for (int k = 0; k < kAdiGraphSteps && rc == FDW_OK; ++k) rc = adi_step<T>(s, false, s->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->cap, &g);
+    if (rc != FDW_OK || e != hipSuccess || !g || hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        s->exec = nullptr;
+        s->graph_failed = true;
+    }
+    if (g) hipGraphDestroy(g);
 }
 
 template <typename T>
@@ -671,11 +702,25 @@ int fdw_adi_step_n(fdw_adi* s, int64_t n)
 {
     if (!s) return FDW_EINVAL;
     if (n < 0) return adi_fail(s, FDW_EINVAL, "n must be >= 0");
-    for (int64_t k = 0; k < n; ++k) {
+    const bool f32 = s->p.dtype == FDW_F32;
+    int64_t k = 0;
+    while (k < n) {
         const bool start = s->n == 0;
-        const int rc = (s->p.dtype == FDW_F32) ? adi_step<float>(s, start) : adi_step<double>(s, start);
+        if (!start && n - k >= kAdiGraphSteps && !s->graph_failed) {
+            // runs of kAdiGraphSteps steps are replayed from a hipGraph (the launch-bound small grids
+            // gain most)
+            if (!s->exec) f32 ? adi_capture<float>(s) : adi_capture<double>(s);
+            if (s->exec) {
+                ADICHK(s, hipGraphLaunch(s->exec, s->stream));
+                s->n += kAdiGraphSteps;
+                k += kAdiGraphSteps;
+                continue;
+            }
+        }
+        const int rc = f32 ? adi_step<float>(s, start, s->stream) : adi_step<double>(s, start, s->stream);
         if (rc) return rc;
         s->n += 1;
+        k += 1;
     }
     return FDW_OK;
 }
@@ -719,6 +764,12 @@ int fdw_adi_reset(fdw_adi* s)
 
 const char* fdw_adi_last_error(const fdw_adi* s) { return s ? s->err.c_str() : "null context"; }
 
-void fdw_adi_destroy(fdw_adi* s) { delete s; }
+void fdw_adi_destroy(fdw_adi* s)
+{
+    if (!s) return;
+    if (s->exec) hipGraphExecDestroy(s->exec);
+    if (s->cap) hipStreamDestroy(s->cap);
+    delete s;
+}
 
 }  // extern "C"

@@ -78,6 +78,38 @@ def test_adi_fp32_longest_lines_vs_oracle(nx, ny):
     assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_adi_graph_replay_equals_step_by_step(dtype_name):
+    """Calls of 16 steps or more replay a captured hipGraph of 16 steps: several replays in one
+    call, and calls with eager work (state read-outs, a reset) between them, give the states of
+    step-by-step launches bit for bit, and the oracle's within the bar."""
+    from paper_2005_11931_amd import fdw
+
+    dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
+    case = _variable_case(131, 97, 120, cfl=3.0)
+    a = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=dt)
+    for _ in range(120 // 8):
+        a.step(8)  # below the graph length: step by step
+    ua, dua, _ = (t.cpu().numpy() if hasattr(t, "cpu") else t for t in a.get_state())
+    a.close()
+    b = fdw.implicit_solver_for_case(case, sigma=0.25, dtype=dt)
+    for rep in range(2):
+        _say("adi graph replay", dtype_name, rep)
+        b.reset()
+        b.step(1)
+        b.step(50)  # three replays and two single steps
+        mid = b.get_state()[0].cpu().numpy()
+        b.step(69)  # four replays and five single steps
+        ub, dub, n = b.get_state()
+        assert n == 120
+        assert np.array_equal(ub.cpu().numpy(), ua) and np.array_equal(dub.cpu().numpy(), dua), rep
+        assert np.isfinite(mid).all()
+    b.close()
+    ref = oracle.adi_forward_case(case, sigma=0.25)["u_cur"]
+    tol = 1e-12 * np.abs(case.u0).max() if dt == fdw.FDW_F64 else 1e-5 * np.abs(ref).max()
+    assert np.abs(ua.astype(np.float64) - ref).max() <= tol
+
+
 def test_adi_sigma_zero_is_the_leapfrog_scheme():
     from paper_2005_11931_amd import fdw
 
