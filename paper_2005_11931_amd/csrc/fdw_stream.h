@@ -312,11 +312,14 @@ __device__ __forceinline__ void sweep_item(const MemberDev& M, int wave, int par
     const int jbase = max(r0 - K, 0);
     const size_t base_el = (size_t)jbase * ld;
     const size_t span = (size_t)(ny - jbase) * ld * sizeof(T);
-    const unsigned int nbytes = (unsigned int)min(span, (size_t)kBufferOutOfRange - 16);
-    const __amdgpu_buffer_rsrc_t ru = plane_rsrc(uin + base_el, nbytes);
-    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(din + base_el, nbytes);
-    const __amdgpu_buffer_rsrc_t rh = plane_rsrc(hp + base_el, nbytes);
-    const __amdgpu_buffer_rsrc_t rhy = plane_rsrc((FACE ? hyp : hp) + base_el, nbytes);
+    const unsigned int nbytes = __builtin_amdgcn_readfirstlane((unsigned int)min(span, (size_t)kBufferOutOfRange - 16));
+    // the descriptors are wave-uniform: build them from values the compiler knows to be uniform
+    // (otherwise, where it cannot prove it - inside the persistent kernel's item loop - every
+    // buffer load is wrapped in a loop over the distinct descriptors of the wave)
+    const __amdgpu_buffer_rsrc_t ru = plane_rsrc(uniform_ptr(uin + base_el), nbytes);
+    const __amdgpu_buffer_rsrc_t rd = plane_rsrc(uniform_ptr(din + base_el), nbytes);
+    const __amdgpu_buffer_rsrc_t rh = plane_rsrc(uniform_ptr(hp + base_el), nbytes);
+    const __amdgpu_buffer_rsrc_t rhy = plane_rsrc(uniform_ptr((FACE ? hyp : hp) + base_el), nbytes);
     const unsigned int row_bytes = (unsigned int)(ld * (int)sizeof(T));
     const unsigned int lane_col = lane_live ? (unsigned int)(cb * (int)sizeof(T)) : kBufferOutOfRange;
 
