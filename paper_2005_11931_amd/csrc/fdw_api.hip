@@ -566,7 +566,7 @@ int run_persistent(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride
     const int64_t tail = steps - phases * K;
     int total = 0;
     for (const MemberDev& md : c->tab) total += md.blocks;
-    int grid = std::min(total, persistent_max_blocks<T>(K, c->C, face_mode));
+    int grid = std::min(total, persistent_max_blocks<T>(K, c->C, face_mode, energy_dev != nullptr));
     if (grid < 1) return fail(c, FDW_EHIP, "persistent launch: no resident blocks");
     int64_t k = koff;
     for (int64_t done = 0; done < phases;) {

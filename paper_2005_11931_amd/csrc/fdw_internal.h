@@ -93,8 +93,9 @@ hipError_t launch_step(const StepArgs& a, int K, int C, int face_mode, int grid,
 template <typename T>
 hipError_t launch_step_persistent(const StepArgs& a, int K, int C, int face_mode, int phases, int grid, int* barrier,
                                   const PersistentExtra& x, hipStream_t s);
+// resident workgroups of the persistent launch variant (with or without energies)
 template <typename T>
-int persistent_max_blocks(int K, int C, int face_mode);
+int persistent_max_blocks(int K, int C, int face_mode, bool energy);
 
 template <typename T>
 // health (may be null): bit 0 set when an energy is non-finite, bit 1 when one exceeds 10x the

@@ -40,10 +40,10 @@ hipError_t launch_persistent_f64c2(const StepArgs& a, int K, int face_mode, int 
                                    const PersistentExtra& x, hipStream_t s);
 hipError_t launch_persistent_f64c1(const StepArgs& a, int K, int face_mode, int phases, int grid, int* bar,
                                    const PersistentExtra& x, hipStream_t s);
-int persistent_max_f32c4(int K, int face_mode);
-int persistent_max_f32c2(int K, int face_mode);
-int persistent_max_f64c2(int K, int face_mode);
-int persistent_max_f64c1(int K, int face_mode);
+int persistent_max_f32c4(int K, int face_mode, bool energy);
+int persistent_max_f32c2(int K, int face_mode, bool energy);
+int persistent_max_f64c2(int K, int face_mode, bool energy);
+int persistent_max_f64c1(int K, int face_mode, bool energy);
 
 template <>
 hipError_t launch_step<float>(const StepArgs& a, int K, int C, int face_mode, int grid, hipStream_t s)
@@ -76,17 +76,17 @@ hipError_t launch_step_persistent<double>(const StepArgs& a, int K, int C, int f
     return hipErrorInvalidValue;
 }
 template <>
-int persistent_max_blocks<float>(int K, int C, int face_mode)
+int persistent_max_blocks<float>(int K, int C, int face_mode, bool energy)
 {
-    if (C == 4) return persistent_max_f32c4(K, face_mode);
-    if (C == 2) return persistent_max_f32c2(K, face_mode);
+    if (C == 4) return persistent_max_f32c4(K, face_mode, energy);
+    if (C == 2) return persistent_max_f32c2(K, face_mode, energy);
     return 0;
 }
 template <>
-int persistent_max_blocks<double>(int K, int C, int face_mode)
+int persistent_max_blocks<double>(int K, int C, int face_mode, bool energy)
 {
-    if (C == 2) return persistent_max_f64c2(K, face_mode);
-    if (C == 1) return persistent_max_f64c1(K, face_mode);
+    if (C == 2) return persistent_max_f64c2(K, face_mode, energy);
+    if (C == 1) return persistent_max_f64c1(K, face_mode, energy);
     return 0;
 }
 

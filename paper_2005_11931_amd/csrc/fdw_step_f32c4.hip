@@ -13,6 +13,6 @@ hipError_t launch_persistent_f32c4(const StepArgs& a, int K, int face_mode, int 
 {
     return launch_persistent_c<float, 4, 6>(a, K, face_mode, phases, grid, bar, x, s);
 }
-int persistent_max_f32c4(int K, int face_mode) { return persistent_max_c<float, 4, 6>(K, face_mode); }
+int persistent_max_f32c4(int K, int face_mode, bool energy) { return persistent_max_c<float, 4, 6>(K, face_mode, energy); }
 
 }  // namespace fdw

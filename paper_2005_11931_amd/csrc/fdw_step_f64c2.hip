@@ -13,6 +13,6 @@ hipError_t launch_persistent_f64c2(const StepArgs& a, int K, int face_mode, int 
 {
     return launch_persistent_c<double, 2, 4>(a, K, face_mode, phases, grid, bar, x, s);
 }
-int persistent_max_f64c2(int K, int face_mode) { return persistent_max_c<double, 2, 4>(K, face_mode); }
+int persistent_max_f64c2(int K, int face_mode, bool energy) { return persistent_max_c<double, 2, 4>(K, face_mode, energy); }
 
 }  // namespace fdw

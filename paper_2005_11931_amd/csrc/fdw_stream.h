@@ -847,13 +847,16 @@ static hipError_t launch_persistent_kc(const StepArgs& a, int face_mode, int pha
 }
 
 template <typename T, int K, int C>
-static int persistent_blocks_kc(int face_mode)
+static int persistent_blocks_kc(int face_mode, bool energy)
 {
     int per_cu = 0;
     const int bs = kWaveSize * kWavesPerBlock;
-    // the energy variant holds more registers: size the grid for it, so both fit
-    hipError_t e = face_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 1, 1>, bs, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<T, K, C, 0, 1>, bs, 0);
+    // the grid is sized for the variant that runs: every one of its blocks must be resident
+    // (a grid sized for the energy variant, which holds more registers, left the plain one at
+    // its occupancy)
+    const void* f = face_mode ? (energy ? (const void*)k_step_persistent<T, K, C, 1, 1> : (const void*)k_step_persistent<T, K, C, 1, 0>)
+                              : (energy ? (const void*)k_step_persistent<T, K, C, 0, 1> : (const void*)k_step_persistent<T, K, C, 0, 0>);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, bs, 0);
     if (e != hipSuccess) return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -877,13 +880,13 @@ static hipError_t launch_persistent_c(const StepArgs& a, int K, int face_mode, i
     }
 }
 template <typename T, int C, int KMAX>
-static int persistent_max_c(int K, int face_mode)
+static int persistent_max_c(int K, int face_mode, bool energy)
 {
     switch (K) {
-    case 1: return persistent_blocks_kc<T, 1, C>(face_mode);
-    case 2: return persistent_blocks_kc<T, 2, C>(face_mode);
-    case 4: return persistent_blocks_kc<T, 4, C>(face_mode);
-    case 8: return KMAX >= 8 ? persistent_blocks_kc<T, (KMAX >= 8 ? 8 : 1), C>(face_mode) : 0;
+    case 1: return persistent_blocks_kc<T, 1, C>(face_mode, energy);
+    case 2: return persistent_blocks_kc<T, 2, C>(face_mode, energy);
+    case 4: return persistent_blocks_kc<T, 4, C>(face_mode, energy);
+    case 8: return KMAX >= 8 ? persistent_blocks_kc<T, (KMAX >= 8 ? 8 : 1), C>(face_mode, energy) : 0;
     default: return 0;
     }
 }
