@@ -653,11 +653,11 @@ __device__ __forceinline__ int find_member(const MemberDev* table, int first, in
     return m;
 }
 
-// The double trace-recording variant (one column per lane) is held to four waves per SIMD (128
-// registers, a few values spilled): its 135 registers otherwise leave three, and the traced
-// forward run of a gradient evaluation measured 5% faster with four.
+// The double trace-recording variant (one column per lane, nodal coefficients) is held to four
+// waves per SIMD (128 registers, a few values spilled): its 135 registers otherwise leave three,
+// and the traced forward run of a gradient evaluation measured 5% faster with four.
 template <typename T, int K, int C, int FACE, int MODE>
-__global__ __launch_bounds__(kWaveSize * kWavesPerBlock, (sizeof(T) == 8 && C == 1 && MODE == 2) ? 4 : 1) void k_step(StepArgs a)
+__global__ __launch_bounds__(kWaveSize * kWavesPerBlock, (sizeof(T) == 8 && C == 1 && FACE == 0 && MODE == 2) ? 4 : 1) void k_step(StepArgs a)
 {
     int lb = xcd_remap(blockIdx.x, a.total_blocks);
     if (a.reverse) lb = a.total_blocks - 1 - lb;

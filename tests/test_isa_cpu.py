@@ -72,9 +72,10 @@ def test_buffer_loads_have_lane_vector_width(asm):
 @pytest.mark.slow
 def test_default_stream_variants_do_not_spill(asm):
     # the defaults: float with 2 columns per lane, K = 8; double with 1 column, K = 8 (every mode).
-    # One exception, by design: the double trace-recording variant (mode 2) is held to 128
-    # registers so that four waves share a SIMD, at the price of a few spilled values (at most
-    # 16 words per lane); it measured faster that way than at three waves without spills.
+    # One exception, by design: the double trace-recording variant with nodal coefficients
+    # (face layout 0, mode 2) is held to 128 registers so that four waves share a SIMD, at the
+    # price of a few spilled values (at most 16 words per lane); it measured faster that way than
+    # at three waves without spills.
     wanted = [("fdw_step_f32c2.hip", "IfLi8ELi2E"), ("fdw_step_f64c1.hip", "IdLi8ELi1E")]
     for unit, tag in wanted:
         names = [n for n in _functions(asm[unit]) if "k_step" in n and tag in n and "persistent" not in n]
@@ -83,7 +84,7 @@ def test_default_stream_variants_do_not_spill(asm):
             meta = _meta(asm[unit], n)
             m = re.search(r"\.amdhsa_private_segment_fixed_size (\d+)", meta)
             assert m, n
-            if unit == "fdw_step_f64c1.hip" and n.endswith("ELi2EEEvNS_8StepArgsE"):
+            if unit == "fdw_step_f64c1.hip" and n.endswith("ELi0ELi2EEEvNS_8StepArgsE"):
                 v = re.search(r"\.amdhsa_next_free_vgpr (\d+)", meta)
                 assert v and int(v.group(1)) <= 128 and int(m.group(1)) <= 64, (n, v and v.group(1), m.group(1))
             else:
