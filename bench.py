@@ -531,7 +531,7 @@ def profile_run(dtype_name: str, workload: str = "point8192"):
     if big:
         # the autotuner's choice on this workload (bench line)
         s.configure(fdw.FDW_CFG_TIME_BLOCK, 8)
-        s.configure(fdw.FDW_CFG_SEGMENT_ROWS, 64)
+        s.configure(fdw.FDW_CFG_SEGMENT_ROWS, 48)
         s.configure(fdw.FDW_CFG_STREAM_POLICY, 3)
     for _ in range(3):  # three solves: the average is over ~150-300 launches, warm-up included
         s.reset()

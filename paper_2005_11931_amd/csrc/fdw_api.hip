@@ -1767,7 +1767,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
             for (int K = 1; K <= 4; ++K) CK.push_back({2, K});
             for (int K = 1; K <= 8; ++K) CK.push_back({1, K});
         }
-        const int Ss[] = {8, 16, 32, 64, 128};
+        const int Ss[] = {8, 16, 32, 48, 64, 96, 128};
         // stream policies: the automatic one, and non-temporal stores with cacheable loads
         // (where that differs from it): which is faster depends on the grids (measured both
         // ways: the 16384^2 float grid gains 18% from cacheable loads, the 8192^2 one loses 5%)

@@ -47,7 +47,7 @@ def test_autotune_choice_cache_and_bitwise_results(tmp_path, dtype_name):
             assert (C == 2 and 1 <= K <= 8) or (C == 4 and 1 <= K <= 6)
         else:
             assert (C == 2 and 1 <= K <= 4) or (C == 1 and 1 <= K <= 8)
-        assert S in (8, 16, 32, 64, 128)
+        assert S in (8, 16, 32, 48, 64, 96, 128)
         assert all(s.steps_taken(m) == 0 for m in range(len(cases)))
         text = cache.read_text()
         P = s.config(fdw.FDW_CFG_STREAM_POLICY)
