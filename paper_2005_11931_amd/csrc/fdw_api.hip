@@ -208,6 +208,17 @@ void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int
     md.strips = (hm.nx + Wv - 1) / Wv;
     md.waves = md.strips * md.segs;
     md.blocks = (md.waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    // energy partials are laid out for this decomposition's waves (the allocation is sized for
+    // the most waves any configuration has: fewer waves leave room for more time-block slots)
+    md.epart_stride = std::max(md.waves, 1);
+}
+
+// time blocks whose energy partials fit member i's allocation at its current decomposition
+int energy_group_cap(const fdw_ctx* c, int i)
+{
+    const HostMember& hm = c->m[i];
+    const size_t cap = (size_t)hm.eslots * (size_t)hm.epart_stride;  // per level, in waves
+    return (int)std::min<size_t>(kMaxEnergySlots, cap / (size_t)std::max(c->tab[i].epart_stride, 1));
 }
 
 // reverse-sweep configurations with one 8-byte value per lane and row (time blocks up to 6)
@@ -494,8 +505,13 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
     const bool trace = any_trace(c);
     int64_t left = steps, k = koff;
     int curK = -1;
-    int gmax = kMaxEnergySlots;  // slots every member holds
-    for (const HostMember& hm : c->m) gmax = std::min(gmax, hm.eslots);
+    // slots every member holds at the current decomposition
+    auto group_cap = [&]() {
+        int g = kMaxEnergySlots;
+        for (int i = 0; i < c->count; ++i) g = std::min(g, energy_group_cap(c, i));
+        return g;
+    };
+    int gmax = group_cap();
     int gK = 0, gcount = 0;
     int64_t gstart = 0;
     while (left > 0) {
@@ -513,6 +529,7 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
             int rc = layout_for_K(c, Kb, c->S_eff, s);
             if (rc) return rc;
             curK = Kb;
+            gmax = group_cap();
         }
         if (energy_dev && gcount == 0) {
             gK = Kb;
