@@ -177,13 +177,13 @@ __global__ __launch_bounds__(kLineThreads) void k_adi_lines(LineArgs A)
     if constexpr (FROM_U) {
         // tau^2 (A u)_{line, i} in flux form, opposite faces added as pairs (as the explicit
         // solver and the oracle form it; the scalings by 1/dx^2 and 1/dy^2 are products with the
-        // reciprocals, which differ from the quotients by rounding only); the loads of six nodes
-        // per thread are issued together
+        // reciprocals, which differ from the quotients by rounding only); the loads of a few
+        // nodes per thread are issued together (3 in double, 6 in float: measured best)
         const T* u = (const T*)A.u + (size_t)line * ld;
         const T* hx = (const T*)A.hx + (size_t)line * ld;
         const T* hy = (const T*)A.hy + (size_t)line * ld;
         const T idx2 = (T)A.idx2, idy2 = (T)A.idy2, tt = (T)A.tt;
-        constexpr int kBatch = 6;
+        constexpr int kBatch = sizeof(T) == 8 ? 3 : 6;
 #pragma unroll
         for (int q0 = 0; q0 < MT; q0 += kBatch) {
             T dv[kBatch];
