@@ -16,7 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-extra] [--ski
        python bench.py --profile-run [--dtype f32|f64]   (short run for rocprofv3: three 800-step
                         forward solves plus three plain copies used to calibrate the counters)
        python bench.py --profile-run --adjoint   (short run of the reverse sweep for rocprofv3)
-       python bench.py --profile-run --workload bathymetry16384|family|implicit4096   (other short runs)
+       python bench.py --profile-run --workload bathymetry16384|family|implicit4096|line256   (other short runs)
        python bench.py --summarize-profile DIR [DIR ...] --out NAME (writes profiles/NAME.txt,
                         and NAME.json with calibrated bytes per launch, from rocprofv3 CSV files)
 """
@@ -141,13 +141,15 @@ def copy_bench(torch, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes / dt / 1e9
 
 
-def small_bench(fdw, torch, I, steps, persistent=False):
-    """The 256^2 FP64 line workload (1000 steps + energy): cache-resident and launch-bound,
+def small_bench(fdw, torch, I, steps, persistent=False, tiles=0):
+    """The 256^2 FP64 line workload (1000 steps + energy): cache-resident and latency-bound,
     reported as microseconds per step with the launch sequence replayed from a graph (one
-    launch per time block, or one persistent launch with grid barriers)."""
+    launch per time block - the small-grid tile kernel by default, the streaming kernel with
+    tiles = 1 - or one persistent launch with grid barriers)."""
     case = I.line_case(n=256, nsteps=1000)
     s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
     s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
+    s.configure(fdw.FDW_CFG_SMALL_TILES, tiles)
     if persistent:
         s.configure(fdw.FDW_CFG_BATCH_MODE, 1)
     h = torch.as_tensor(case.h1, device="cuda")
@@ -580,6 +582,29 @@ def profile_run_implicit():
     log("implicit profile run done")
 
 
+def profile_run_small():
+    """Short run of the 256^2 FP64 line workload for rocprofv3: three 1000-step solves with
+    per-step energy, replayed from a hipGraph, on the small-grid tile kernel and then on the
+    streaming kernel."""
+    import torch
+
+    from paper_2005_11931_amd import fdw
+    from paper_2005_11931_amd import inputs as I
+
+    case = I.line_case(n=256, nsteps=1000)
+    for tiles in (2, 1):
+        s = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+        s.configure(fdw.FDW_CFG_USE_GRAPH, 1)
+        s.configure(fdw.FDW_CFG_SMALL_TILES, tiles)
+        e = torch.empty((1, case.nsteps), dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            s.reset()
+            s.step_into(case.nsteps, e)
+        torch.cuda.synchronize()
+        s.close()
+    log("profile run done: small")
+
+
 def profile_run_adjoint():
     """Short, profiler-friendly run of the reverse sweep: the 2048^2 FP64 receiver-misfit
     workload cut to 512 steps (checkpoints every 64), one forward solve recording traces and
@@ -691,7 +716,7 @@ def main():
         ap.add_argument("--dtype", default="f32")
         ap.add_argument("--adjoint", action="store_true")
         ap.add_argument("--workload", default="point8192",
-                        choices=["point8192", "bathymetry16384", "family", "implicit4096"])
+                        choices=["point8192", "bathymetry16384", "family", "implicit4096", "line256"])
         a = ap.parse_args()
         if a.adjoint:
             profile_run_adjoint()
@@ -699,6 +724,8 @@ def main():
             profile_run_family()
         elif a.workload == "implicit4096":
             profile_run_implicit()
+        elif a.workload == "line256":
+            profile_run_small()
         else:
             profile_run(a.dtype, a.workload)
         return
@@ -839,8 +866,10 @@ def main():
         torch.cuda.empty_cache()
         log("small 256^2 fp64 line")
         sm = small_bench(fdw, torch, I, args.steps)
+        sms = small_bench(fdw, torch, I, args.steps, tiles=1)
         smp = small_bench(fdw, torch, I, args.steps, persistent=True)
         out["small"] = {"us_per_step": round(sm["us_per_step"], 3), "time_block": sm["K"],
+                        "streaming_kernel_us_per_step": round(sms["us_per_step"], 3),
                         "persistent_us_per_step": round(smp["us_per_step"], 3),
                         "workload": "256x256 FP64 line singularity h = 1 + 2 phi_0.05(x), 1000 steps with per-step "
                                     "energy, launch sequence replayed from a hipGraph (cache-resident)"}

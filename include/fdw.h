@@ -255,10 +255,20 @@ enum {
                                      reverse order, so the rows a launch wrote last are read first by
                                      the next one (1-3% faster where measured); 0: one fixed order;
                                      results are identical */
-    FDW_CFG_STREAM_POLICY = 13    /* row accesses of the forward stencil: 0 (default) non-temporal when the
+    FDW_CFG_STREAM_POLICY = 13,   /* row accesses of the forward stencil: 0 (default) non-temporal when the
                                      working set exceeds the last-level cache; 1 non-temporal loads and
                                      stores; 2 cacheable loads and stores; 3 non-temporal stores only;
                                      4 non-temporal loads only (float); results are identical */
+    FDW_CFG_SMALL_TILES = 14,     /* small-grid kernel: one workgroup per tile of 48 owned columns,
+                                     its waves advancing the tile level by level together.  0 (default):
+                                     used where every member has at most 768 x 768 nodes; 1: never;
+                                     2: wherever allowed.  Never with receiver traces or the persistent
+                                     launch (the streaming kernel runs those steps).  States are
+                                     identical bit for bit; energies agree to rounding (other partial
+                                     sums) */
+    FDW_CFG_TILE_ROWS = 15        /* rows per tile of the small-grid kernel (16 halo rows included):
+                                     32, 48 or 64 (0 = automatic: the tallest that gives a launch at
+                                     least 150 tiles, else 32) */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);

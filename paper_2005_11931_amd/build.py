@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libfdw.so")
 SOURCES = ["fdw_api.hip", "fdw_kernels.hip", "fdw_adjoint.hip", "fdw_noalloc.hip", "fdw_implicit.hip", "fdw_step_f32c4.hip", "fdw_step_f32c2.hip",
-           "fdw_step_f64c2.hip", "fdw_step_f64c1.hip"]
+           "fdw_step_f64c2.hip", "fdw_step_f64c1.hip", "fdw_tile.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -4,6 +4,7 @@
 // Section 2 eq. (2.1), on the grid of Section 3.3 (see include/fdw.h).
 #include "../../include/fdw.h"
 #include "fdw_internal.h"
+#include "fdw_tile.h"
 
 #include <hip/hip_runtime.h>
 
@@ -90,6 +91,9 @@ struct fdw_ctx {
     int check_energy = 1;  // fdw_step_n checks the energies it computes (FDW_CFG_CHECK_ENERGY)
     int item_order = 1;    // FDW_CFG_ITEM_ORDER: 1 walks every other launch's blocks in reverse
     int stream_policy = 0; // FDW_CFG_STREAM_POLICY: 0 automatic, 1 non-temporal, 2 cacheable
+    int tile_mode = 0;     // FDW_CFG_SMALL_TILES: 0 automatic, 1 never, 2 wherever allowed
+    int tile_rows = 0;     // FDW_CFG_TILE_ROWS: rows per tile (0 = automatic)
+    bool tiles_now = false;  // the member table holds the tile decomposition
     int test_flag_barrier = 0;  // FDW_CFG_TEST_BARRIER_FLAG: mark the next persistent call as timed out
     bool used_persistent = false;  // the last step_n ran the persistent launch
     int C = 4;  // columns per lane of the streaming kernels
@@ -213,6 +217,36 @@ void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int
     md.epart_stride = std::max(md.waves, 1);
 }
 
+// rows per tile of the small-grid kernel: the tallest tile (64, 48 or 32 rows: 16, 12 or 8
+// waves) that still gives the launch at least 150 tiles, else 32.  Measured (256^2 .. 724^2,
+// FP64 and FP32, time block 8): the per-tile time grows with the waves sharing a SIMD, the
+// redundant halo work with the tile count; about one tile per CU balances the two.
+int tile_rows(const fdw_ctx* c)
+{
+    if (c->tile_rows > 0) return c->tile_rows;
+    for (int rows : {64, 48}) {
+        int64_t tiles = 0;
+        for (const HostMember& hm : c->m)
+            tiles += (int64_t)((hm.nx + kTileCols - 1) / kTileCols) *
+                     ((hm.ny + rows - 2 * kTileHalo - 1) / (rows - 2 * kTileHalo));
+        if (tiles >= 150) return rows;
+    }
+    return 32;
+}
+
+// The small-grid decomposition: one tile per workgroup, independent of the time block (its halo
+// covers the deepest one).  waves = blocks = tiles (one energy partial per tile and level).
+void decompose_tile(const fdw_ctx* c, const HostMember& hm, MemberDev& md)
+{
+    const int rows = tile_rows(c);
+    md.seg_rows = rows - 2 * kTileHalo;
+    md.segs = (hm.ny + md.seg_rows - 1) / md.seg_rows;
+    md.strips = (hm.nx + kTileCols - 1) / kTileCols;
+    md.waves = md.strips * md.segs;
+    md.blocks = md.waves;
+    md.epart_stride = std::max(md.waves, 1);
+}
+
 // time blocks whose energy partials fit member i's allocation at its current decomposition
 int energy_group_cap(const fdw_ctx* c, int i)
 {
@@ -265,7 +299,10 @@ int layout_for_K(fdw_ctx* c, int K, int S, hipStream_t st = nullptr)
     int base = 0;
     for (int i = 0; i < c->count; ++i) {
         MemberDev& md = c->tab[i];
-        decompose(c, c->m[i], md, S, K);
+        if (c->tiles_now)
+            decompose_tile(c, c->m[i], md);
+        else
+            decompose(c, c->m[i], md, S, K);
         md.block_base = base;
         base += md.blocks;
     }
@@ -461,6 +498,11 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
     int face_mode = c->m[first].face;
     for (int i = first; i < first + nm; ++i)
         if (c->m[i].face != face_mode) face_mode = -1;
+    if (c->tiles_now && trace) return fail(c, FDW_ENOTSUP, "tile decomposition with receiver traces");
+    auto launch = [&](const StepArgs& sa, int face, int grid) {
+        return c->tiles_now ? launch_step_tile<T>(sa, K, face, tile_rows(c) / kTileRowsPerWave, grid, s)
+                            : launch_step<T>(sa, K, c->C, face, grid, s);
+    };
     if (face_mode < 0) {
         // mixed layouts in one batch: launch per member
         for (int i = first; i < first + nm; ++i) {
@@ -468,7 +510,7 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
             a.nmembers = 1;
             a.block_offset = c->tab[i].block_base;
             a.total_blocks = c->tab[i].blocks;
-            HIPCHK(c, launch_step<T>(a, K, c->C, c->m[i].face, a.total_blocks, s));
+            HIPCHK(c, launch(a, c->m[i].face, a.total_blocks));
         }
         return FDW_OK;
     }
@@ -481,7 +523,7 @@ int launch_block(fdw_ctx* c, int first, int nm, int K, bool energy, bool trace, 
         }
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
     }
-    HIPCHK(c, launch_step<T>(a, K, c->C, face_mode, total, s));
+    HIPCHK(c, launch(a, face_mode, total));
     if (timed) {
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
         c->ev_used += 2;
@@ -654,12 +696,35 @@ void replay_bookkeeping(fdw_ctx* c, int64_t steps, bool persistent)
     }
 }
 
+// Whether a step_n call runs the small-grid tile kernel: not with receiver traces (the streaming
+// kernel records them) or the persistent launch; automatically where every member has at most
+// kTileAutoNodes nodes (there the streaming kernel's few, long work items leave most of the
+// device idle: measured faster up to 724^2, slower at 1024^2).
+constexpr int64_t kTileAutoNodes = (int64_t)768 * 768;
+bool want_tiles(const fdw_ctx* c)
+{
+    if (c->tile_mode == 1 || c->batch_mode == 1 || any_trace(c)) return false;
+    if (c->tile_mode == 2) return true;
+    for (const HostMember& hm : c->m)
+        if ((int64_t)hm.nx * hm.ny > kTileAutoNodes) return false;
+    return true;
+}
+
 template <typename T>
 int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
 {
     for (int i = 0; i < c->count; ++i)
         if (!c->m[i].coeff) return fail(c, FDW_ESTATE, "fdw_set_coeff has not been called for member " + std::to_string(i));
     if (n == 0) return FDW_OK;
+    {
+        // both kernels produce the same states bit for bit: the choice may change between calls
+        const bool tiles = want_tiles(c);
+        if (tiles != c->tiles_now) {
+            c->tiles_now = tiles;
+            const int rc = layout_for_K(c, choose_K(c), c->S_eff);
+            if (rc) return rc;
+        }
+    }
     bool any0 = false, any1 = false;
     for (const HostMember& hm : c->m) (hm.n == 0 ? any0 : any1) = true;
     int64_t done = 0;
@@ -707,7 +772,8 @@ int step_n_impl(fdw_ctx* c, int64_t n, double* energy_dev)
         uint64_t pairs = 0;
         if (c->count <= 64)
             for (int i = 0; i < c->count; ++i) pairs |= (uint64_t)(c->tab[i].cur0 & 1) << i;
-        const auto key = std::make_tuple(left, choose_K(c) + 16 * (int)persistent, (const double*)energy_dev,
+        const auto key = std::make_tuple(left, choose_K(c) + 16 * (int)persistent + 32 * (int)c->tiles_now,
+                                         (const double*)energy_dev,
                                          (int)(c->launches & 1), (int)done, pairs);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -1353,6 +1419,14 @@ int fdw_configure(fdw_ctx* c, int32_t key, int64_t v)
         if (v < 0 || v > 4) return fail(c, FDW_EINVAL, "stream policy must be 0..4");
         c->stream_policy = (int)v;
         break;
+    case FDW_CFG_SMALL_TILES:
+        if (v < 0 || v > 2) return fail(c, FDW_EINVAL, "small-grid tiles must be 0 (automatic), 1 (off) or 2 (on)");
+        c->tile_mode = (int)v;
+        break;
+    case FDW_CFG_TILE_ROWS:
+        if (v != 0 && v != 32 && v != 48 && v != 64) return fail(c, FDW_EINVAL, "tile rows must be 0, 32, 48 or 64");
+        c->tile_rows = (int)v;
+        break;
     default: return fail(c, FDW_EINVAL, "unknown configuration key");
     }
     invalidate_graphs(c);
@@ -1410,6 +1484,8 @@ int64_t fdw_get_config(const fdw_ctx* c, int32_t key)
     case FDW_CFG_TEST_BARRIER_FLAG: return c->test_flag_barrier;
     case FDW_CFG_ITEM_ORDER: return c->item_order;
     case FDW_CFG_STREAM_POLICY: return c->stream_policy;
+    case FDW_CFG_SMALL_TILES: return c->tile_mode;
+    case FDW_CFG_TILE_ROWS: return tile_rows(c);
     default: return -1;
     }
 }
@@ -1795,6 +1871,9 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         // the choice is the best for the way the caller steps; the energy check is off meanwhile
         const int saveCheck = c->check_energy;
         c->check_energy = 0;
+        // the search times the streaming kernel (the small-grid tiles have no such parameters)
+        const int saveTiles = c->tile_mode;
+        c->tile_mode = 1;
         hipEvent_t e0, e1;
         HIPCHK(c, hipEventCreate(&e0));
         HIPCHK(c, hipEventCreate(&e1));
@@ -1851,6 +1930,7 @@ extern "C" int fdw_autotune(fdw_ctx* c, int32_t steps, int64_t* best_out)
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         c->check_energy = saveCheck;
+        c->tile_mode = saveTiles;
         bestC_out = bestC;
         bestP_out = bestP;
         cache_store(key, bestK, bestS, bestC, bestP);

@@ -31,6 +31,7 @@ FDW_ALLOW_UNSTABLE, FDW_ALLOW_ZERO_H = 1, 2
 FDW_CFG_TIME_BLOCK, FDW_CFG_SEGMENT_ROWS, FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE, FDW_CFG_TIMING = 1, 2, 3, 4, 5
 FDW_CFG_LANE_COLUMNS, FDW_CFG_ADJ_TIME_BLOCK, FDW_CFG_ADJ_LANE_COLUMNS, FDW_CFG_ADJ_SEGMENT_ROWS = 6, 7, 8, 9
 FDW_CFG_CHECK_ENERGY, FDW_CFG_TEST_BARRIER_FLAG, FDW_CFG_ITEM_ORDER, FDW_CFG_STREAM_POLICY = 10, 11, 12, 13
+FDW_CFG_SMALL_TILES, FDW_CFG_TILE_ROWS = 14, 15
 
 EXPORTED = [
     "fdw_workspace_bytes", "fdw_init", "fdw_set_coeff", "fdw_step_n", "fdw_energy", "fdw_record_traces",

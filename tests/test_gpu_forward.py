@@ -28,11 +28,16 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run(case, dtype, nsteps, K=0, S=0, energy=False, separate_h2=False, graph=0, snapshots=(), flags=0, C=0):
+def _run(case, dtype, nsteps, K=0, S=0, energy=False, separate_h2=False, graph=0, snapshots=(), flags=0, C=0,
+         tiles=0, tile_rows=0):
     import torch
 
     fdw = _fdw()
     s = fdw.solver_for_case(case, dtype=dtype, separate_h2=separate_h2, flags=flags)
+    if tiles:
+        s.configure(fdw.FDW_CFG_SMALL_TILES, tiles)
+    if tile_rows:
+        s.configure(fdw.FDW_CFG_TILE_ROWS, tile_rows)
     if C:
         s.configure(fdw.FDW_CFG_LANE_COLUMNS, C)
     if K:
@@ -75,9 +80,10 @@ def test_line_fp64_parity_with_energy_and_snapshots():
     # one call of 1000 steps: the energies of up to 64 time blocks are summed by one
     # finalisation, so a call of 250 blocks of 4 steps spans four groups (and a graph replay
     # repeats them)
-    for K, graph in ((4, 0), (8, 1)):
-        _say("line fp64 one call, K", K, "graph", graph)
-        snaps1, E1 = _run(case, fdw.FDW_F64, 1000, K=K, energy=True, graph=graph)
+    # (the small-grid tile kernel runs this grid by default; the streaming kernel as well)
+    for K, graph, tiles in ((4, 0, 0), (8, 1, 0), (8, 1, 1), (3, 0, 1)):
+        _say("line fp64 one call, K", K, "graph", graph, "tiles", tiles)
+        snaps1, E1 = _run(case, fdw.FDW_F64, 1000, K=K, energy=True, graph=graph, tiles=tiles)
         assert np.abs(E1 - ref_e).max() <= 1e-12 * ref_e[0], K
         assert np.array_equal(snaps1[1000][0], snaps[1000][0])
 
@@ -129,7 +135,8 @@ def test_ragged_sizes_vs_oracle(nx, ny, dtype_name, layout):
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
 @pytest.mark.parametrize("layout", ["nodal", "face"])
 def test_variants_bitwise(dtype_name, layout):
-    """Every time block K and segment length gives the same bits."""
+    """Every time block K and segment length of the streaming kernel, and the small-grid tile
+    kernel at every tile height and time block, give the same bits."""
     fdw = _fdw()
     nx, ny = 611, 203
     rng = np.random.default_rng(5)
@@ -151,7 +158,7 @@ def test_variants_bitwise(dtype_name, layout):
         for K in Ks:
             for S in (16, 48, 1024):
                 _say("variant", dtype_name, layout, C, K, S)
-                snaps, E = _run(case, dt, N, K=K, S=S, C=C, energy=True, separate_h2=(layout == "face"))
+                snaps, E = _run(case, dt, N, K=K, S=S, C=C, energy=True, separate_h2=(layout == "face"), tiles=1)
                 u, du = snaps[N]
                 if base is None:
                     base = (u, du, E)
@@ -161,6 +168,14 @@ def test_variants_bitwise(dtype_name, layout):
                     # in blocks of rows for float storage)
                     etol = 1e-13 if dt == fdw.FDW_F64 else 1e-7
                     assert np.abs(E - base[2]).max() <= etol * abs(base[2][0])
+    for rows in (32, 48, 64):
+        for K in (1, 2, 5, 8):
+            _say("tile variant", dtype_name, layout, rows, K)
+            snaps, E = _run(case, dt, N, K=K, energy=True, separate_h2=(layout == "face"), tiles=2, tile_rows=rows)
+            u, du = snaps[N]
+            assert np.array_equal(u, base[0]) and np.array_equal(du, base[1]), (rows, K)
+            etol = 1e-13 if dt == fdw.FDW_F64 else 1e-7
+            assert np.abs(E - base[2]).max() <= etol * abs(base[2][0])
 
 
 @pytest.mark.parametrize("dtype_name", ["f64", "f32"])
@@ -176,6 +191,7 @@ def test_item_order_and_stream_policy_bitwise(dtype_name):
 
     def run(order, policy, graph):
         s = fdw.family_solver(fam, dtype=dt)
+        s.configure(fdw.FDW_CFG_SMALL_TILES, 1)  # the streaming kernel (these grids default to tiles)
         s.configure(fdw.FDW_CFG_ITEM_ORDER, order)
         s.configure(fdw.FDW_CFG_STREAM_POLICY, policy)
         s.configure(fdw.FDW_CFG_USE_GRAPH, graph)
@@ -200,6 +216,88 @@ def test_item_order_and_stream_policy_bitwise(dtype_name):
             s.configure(fdw.FDW_CFG_STREAM_POLICY, 5)
         finally:
             s.close()
+
+
+@pytest.mark.parametrize("dtype_name", ["f64", "f32"])
+def test_small_grid_tiles_vs_streaming_and_oracle(dtype_name):
+    """The small-grid tile kernel (forced on, automatic, off) on a family of ragged grids in both
+    coefficient layouts: states bit for bit equal to the streaming kernel's, energies to
+    rounding, both against the FP64 oracle; calls of uneven lengths, plain launches and hipGraph
+    replay, a member returned to step 0 mid-run, and traces switched on for one call (those
+    steps run on the streaming kernel)."""
+    import torch
+
+    fdw = _fdw()
+    dt = fdw.FDW_F64 if dtype_name == "f64" else fdw.FDW_F32
+    rng = np.random.default_rng(77)
+    cases = []
+    for k, (nx, ny) in enumerate(((3, 3), (49, 17), (97, 130), (300, 70), (130, 611))):
+        x, y, X, Y = I.mesh(nx, ny)
+        h1 = 0.5 + rng.uniform(0, 1, (ny, nx))
+        h2 = (0.4 + rng.uniform(0, 1, (ny, nx))) if k % 2 else None
+        u0 = I.zero_ring(np.exp(-((X - 0.1) ** 2 + Y**2) / 0.1) + 0.05 * rng.normal(size=(ny, nx)))
+        u1 = I.zero_ring(0.2 * np.sin(2 * X) * np.cos(3 * Y))
+        dx, dy = 2.0 / (nx - 1), 2.0 / (ny - 1)
+        hm = max(h1.max(), h2.max() if h2 is not None else 0)
+        tau = 0.45 / math.sqrt(hm * (1 / dx**2 + 1 / dy**2))
+        cases.append(I.Case("tile%d" % k, nx, ny, -1, 1, -1, 1, tau, 75, h1, h2, u0, u1))
+    N = 75
+
+    def run(tiles, graph, rows=0):
+        s = fdw.family_solver(cases, dtype=dt)
+        s.configure(fdw.FDW_CFG_SMALL_TILES, tiles)
+        if rows:
+            s.configure(fdw.FDW_CFG_TILE_ROWS, rows)
+        s.configure(fdw.FDW_CFG_USE_GRAPH, graph)
+        E = [s.step(k, energy=True).cpu().numpy() for k in (1, 20, 21)]
+        s.reset(2)  # member 2 restarts while the others go on
+        E.append(s.step(33, energy=True).cpu().numpy())
+        st = _states_of(s)
+        s.close()
+        return st, E
+
+    def _states_of(s):
+        return [tuple(t.cpu().numpy().astype(np.float64) for t in s.get_state(m)[:2]) for m in range(s.count)]
+
+    base, Eb = run(1, 0)
+    for tiles, graph, rows in ((2, 0, 0), (2, 1, 0), (0, 1, 48), (2, 0, 64)):
+        _say("tiles", tiles, "graph", graph, "rows", rows, dtype_name)
+        st, E = run(tiles, graph, rows)
+        for m in range(len(cases)):
+            assert np.array_equal(st[m][0], base[m][0]) and np.array_equal(st[m][1], base[m][1]), (tiles, graph, m)
+        etol = 1e-13 if dt == fdw.FDW_F64 else 1e-7
+        for a, b in zip(E, Eb):
+            assert np.abs(a - b).max() <= etol * np.abs(b).max(), (tiles, graph)
+    # against the oracle (member 2 was restarted: it stands at step 33, the others at 75)
+    for m, case in enumerate(cases):
+        n = 33 if m == 2 else N
+        ref = oracle.forward_case(case, nsteps=n)
+        u, du = base[m]
+        if dt == fdw.FDW_F64:
+            assert np.abs(u - ref["u_cur"]).max() <= 1e-12, m
+            assert np.abs((u - du) - ref["u_prev"]).max() <= 1e-12, m
+        else:
+            assert np.abs(u - ref["u_cur"]).max() <= 1e-5 * max(np.abs(ref["u_cur"]).max(), 1e-30), m
+    # traces for one call: the streaming kernel runs those steps, the tiles the ones around them
+    rec = np.array([[40, 60], [41, 60], [5, 100]], dtype=np.int32)
+    ref = oracle.forward_case(cases[2], receivers=rec)
+    s = fdw.solver_for_case(cases[2], dtype=dt)
+    s.configure(fdw.FDW_CFG_SMALL_TILES, 2)
+    s.step(30)
+    tr = s.record_traces(torch.as_tensor(rec))
+    s.step(20)
+    s.record_traces(None)
+    s.step(25)
+    u, du, n = s.get_state()
+    t = tr.cpu().numpy().astype(np.float64)
+    s.close()
+    assert n == N
+    full = oracle.forward_case(cases[2])
+    if dt == fdw.FDW_F64:
+        assert np.abs(t[31:51] - ref["traces"][31:51]).max() <= 1e-12
+        assert np.abs(u.cpu().numpy() - full["u_cur"]).max() <= 1e-12
+    else:
+        assert np.abs(t[31:51] - ref["traces"][31:51]).max() <= 1e-5 * np.abs(ref["traces"]).max()
 
 
 def test_graph_replay_matches_plain():

@@ -16,7 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2005_11931_amd", "csrc")
 UNITS = ["fdw_step_f32c2.hip", "fdw_step_f32c4.hip", "fdw_step_f64c2.hip", "fdw_step_f64c1.hip",
-         "fdw_adjoint.hip", "fdw_kernels.hip"]
+         "fdw_adjoint.hip", "fdw_kernels.hip", "fdw_tile.hip", "fdw_implicit.hip", "fdw_noalloc.hip"]
 
 
 def _asm(unit, tmp):
@@ -89,6 +89,23 @@ def test_default_stream_variants_do_not_spill(asm):
                 assert v and int(v.group(1)) <= 128 and int(m.group(1)) <= 64, (n, v and v.group(1), m.group(1))
             else:
                 assert int(m.group(1)) == 0, (n, m.group(1))
+
+
+@pytest.mark.slow
+def test_small_grid_tile_kernels_do_not_spill(asm):
+    names = [n for n in _functions(asm["fdw_tile.hip"]) if "k_step_tile" in n]
+    assert len(names) == 8, names
+    for n in names:
+        meta = _meta(asm["fdw_tile.hip"], n)
+        m = re.search(r"\.amdhsa_private_segment_fixed_size (\d+)", meta)
+        v = re.search(r"\.amdhsa_next_free_vgpr (\d+)", meta)
+        # 1024-thread workgroups: at most 128 registers per lane
+        assert m and int(m.group(1)) == 0 and v and int(v.group(1)) <= 128, (n, m and m.group(1), v and v.group(1))
+        # plane reads are buffer loads of one element (out-of-range rows read 0 without a branch);
+        # a global load here would sit under a lane test and be waited for on the spot
+        body = _functions(asm["fdw_tile.hip"])[n]
+        loads = set(re.findall(r"\b((?:buffer|global)_load_\w+)", body))
+        assert loads == ({"buffer_load_dwordx2"} if "IdLi" in n else {"buffer_load_dword"}), (n, loads)
 
 
 @pytest.mark.slow
