@@ -453,6 +453,21 @@ int record_hook(fdw_ctx* c, hipStream_t s)
     return store_checkpoint(c, hm, cu, cd, hm.u[hm.cur], hm.d[hm.cur], s);
 }
 
+// Checkpoint slot of the recorded member for step n (false: no checkpoint is stored there).
+bool checkpoint_slot(fdw_ctx* c, const HostMember& hm, int64_t n, void** cu, void** cd)
+{
+    const int ck = c->rec.ck;
+    if (c->rec.member < 0 || n < 1 || n % ck != 0 || n >= hm.N) return false;
+    const AdjLayout L = adj_layout(c, hm, ck);
+    const int64_t k = n / ck - 1;
+    if (k >= L.nck) return false;
+    const size_t es = elem_size(c->dtype);
+    char* base = (char*)c->rec.ws + align_up(sizeof(MemberDev), kAlign) + 8 * L.plane + 2 * L.plane64;
+    *cu = plane_origin(base + (size_t)(2 * k) * L.plane, hm.ld, es);
+    *cd = plane_origin(base + (size_t)(2 * k + 1) * L.plane, hm.ld, es);
+    return true;
+}
+
 // Steps until the recorded member's next checkpoint (a time block must not cross it).
 int64_t steps_to_checkpoint(const fdw_ctx* c)
 {
@@ -556,6 +571,24 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
     int gmax = group_cap();
     int gK = 0, gcount = 0;
     int64_t gstart = 0;
+    // Checkpoint recording: a launch that ends on a checkpoint step (other than the call's last)
+    // writes the recorded member's state straight into the checkpoint slot, and the next launch
+    // reads it from there - the member's table pointers are redirected around those launches
+    // instead of copying the state after them (two planes read and written per checkpoint).
+    const int rm = c->rec.member;
+    void* prev_u = nullptr;
+    void* prev_d = nullptr;  // slot the previous launch wrote (null: the ping-pong buffer)
+    auto point_member = [&](void* in_u, void* in_d, void* out_u, void* out_d) -> int {
+        HostMember& hm = c->m[rm];
+        MemberDev& md = c->tab[rm];
+        const int i = hm.cur;
+        if (md.u[i] == in_u && md.d[i] == in_d && md.u[i ^ 1] == out_u && md.d[i ^ 1] == out_d) return FDW_OK;
+        md.u[i] = in_u;
+        md.d[i] = in_d;
+        md.u[i ^ 1] = out_u;
+        md.d[i ^ 1] = out_d;
+        return push_member(c, rm, s);
+    };
     while (left > 0) {
         const int Kb = (int)std::min<int64_t>(std::min<int64_t>(K, left), steps_to_checkpoint(c));
         // energies: consecutive time blocks of one length write their partials into successive
@@ -577,6 +610,18 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
             gK = Kb;
             gstart = k;
         }
+        bool direct = false;
+        if (rm >= 0) {
+            const HostMember& hm = c->m[rm];
+            void* su = nullptr;
+            void* sd = nullptr;
+            direct = left > Kb && checkpoint_slot(c, hm, hm.n + Kb, &su, &sd);
+            int rc = point_member(prev_u ? prev_u : hm.u[hm.cur], prev_d ? prev_d : hm.d[hm.cur],
+                                  direct ? su : hm.u[hm.cur ^ 1], direct ? sd : hm.d[hm.cur ^ 1]);
+            if (rc) return rc;
+            prev_u = direct ? su : nullptr;
+            prev_d = direct ? sd : nullptr;
+        }
         int rc = launch_block<T>(c, 0, c->count, Kb, energy_dev != nullptr, trace, s, energy_dev ? gcount : 0);
         if (rc) return rc;
         if (energy_dev) ++gcount;
@@ -586,14 +631,23 @@ int run_blocks(fdw_ctx* c, int64_t steps, double* energy_dev, int64_t stride, in
             hm.n += Kb;
             hm.cur ^= 1;
         }
-        rc = record_hook(c, s);
-        if (rc) return rc;
+        if (!direct) {
+            rc = record_hook(c, s);  // a copy, where the state is in the ping-pong buffer
+            if (rc) return rc;
+        }
         left -= Kb;
         k += Kb;
     }
     if (energy_dev && gcount > 0)
         HIPCHK(c, launch_energy_finalize<T>(c->tab_dev, 0, c->count, gK, energy_dev, stride, gstart, health_word(c), s,
                                             0, gcount));
+    if (rm >= 0) {
+        // the call's last launch wrote the ping-pong buffer: the table points at the member's own
+        // buffers again
+        const HostMember& hm = c->m[rm];
+        int rc = point_member(hm.u[hm.cur], hm.d[hm.cur], hm.u[hm.cur ^ 1], hm.d[hm.cur ^ 1]);
+        if (rc) return rc;
+    }
     if (curK != K) {
         // leave the table in the main configuration
         int rc = layout_for_K(c, K, c->S_eff, s);

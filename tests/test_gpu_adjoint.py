@@ -259,6 +259,26 @@ def test_recorded_checkpoints_equal_replay(ck):
     assert np.abs(tr.cpu().numpy() - ref["traces"]).max() <= 1e-12
     g_rec = s.adjoint(rec, tg, ckpt_every=ck).cpu().numpy()
     assert np.array_equal(g_rec, g_replay)
+    # the same recording made in calls of uneven lengths (one ending on a checkpoint step, where
+    # the state is copied; inside a call the launch ending on a checkpoint writes the slot
+    # itself), with and without traces (this grid runs the small-grid kernel without them)
+    for traced in (True, False):
+        s2 = fdw.solver_for_case(case, dtype=fdw.FDW_F64)
+        s2.record_checkpoints(ck)
+        if traced:
+            s2.record_traces(rec)
+        done = 0
+        for k in (3, ck, 2 * ck - 3, case.nsteps):
+            k = min(k, case.nsteps - done)
+            if k > 0:
+                s2.step(k)
+                done += k
+        g_rec3 = s2.adjoint(rec, tg, ckpt_every=ck).cpu().numpy()
+        u2, _, n2 = s2.get_state()
+        s2.close()
+        assert n2 == case.nsteps
+        assert np.array_equal(g_rec3, g_replay), traced
+        assert np.abs(u2.cpu().numpy() - ref["u_cur"]).max() <= 1e-12
     # the recording stays usable for a second trace gradient
     g_rec2 = s.adjoint(rec, 2.0 * tg, ckpt_every=ck).cpu().numpy()
     assert np.allclose(g_rec2, 2.0 * g_replay, rtol=1e-12, atol=0)
