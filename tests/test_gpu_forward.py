@@ -278,6 +278,27 @@ def test_small_grid_tiles_vs_streaming_and_oracle(dtype_name):
             assert np.abs((u - du) - ref["u_prev"]).max() <= 1e-12, m
         else:
             assert np.abs(u - ref["u_cur"]).max() <= 1e-5 * max(np.abs(ref["u_cur"]).max(), 1e-30), m
+    # tiles forced onto a grid beyond the automatic range (a ragged 2100 x 1100 float grid, 64-row
+    # tiles): the same bits as the streaming kernel
+    rng2 = np.random.default_rng(78)
+    nx2, ny2 = 2100, 1100
+    x, y, X, Y = I.mesh(nx2, ny2)
+    h12 = 0.5 + rng2.uniform(0, 1, (ny2, nx2))
+    u02 = I.zero_ring(np.exp(-((X - 0.2) ** 2 + Y**2) / 0.05) + 0.01 * rng2.normal(size=(ny2, nx2)))
+    tau2 = 0.45 / math.sqrt(h12.max() * (1 / (2.0 / (nx2 - 1)) ** 2 + 1 / (2.0 / (ny2 - 1)) ** 2))
+    wide = I.Case("wide", nx2, ny2, -1, 1, -1, 1, tau2, 21, h12, None, u02, np.zeros_like(u02))
+    got = []
+    for tiles in (1, 2):
+        _say("wide grid, tiles", tiles, dtype_name)
+        s = fdw.solver_for_case(wide, dtype=dt)
+        s.configure(fdw.FDW_CFG_SMALL_TILES, tiles)
+        s.configure(fdw.FDW_CFG_TILE_ROWS, 64)
+        e = s.step(21, energy=True).cpu().numpy()
+        u, du, _ = s.get_state()
+        got.append((u.cpu().numpy(), du.cpu().numpy(), e))
+        s.close()
+    assert np.array_equal(got[0][0], got[1][0]) and np.array_equal(got[0][1], got[1][1])
+    assert np.abs(got[0][2] - got[1][2]).max() <= (1e-13 if dt == fdw.FDW_F64 else 1e-6) * np.abs(got[0][2]).max()
     # traces for one call: the streaming kernel runs those steps, the tiles the ones around them
     rec = np.array([[40, 60], [41, 60], [5, 100]], dtype=np.int32)
     ref = oracle.forward_case(cases[2], receivers=rec)
