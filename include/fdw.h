@@ -284,7 +284,9 @@ int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);
  * file named by the FDW_AUTOTUNE_CACHE environment variable (if set) under a key of
  * (device arch, storage type, member sizes and layouts, launch mode).  The candidates run in
  * the context's own launch mode (FDW_CFG_USE_GRAPH, FDW_CFG_BATCH_MODE; the persistent launch
- * only takes time blocks 1, 2, 4, 8).  steps: time steps per candidate
+ * only takes time blocks 1, 2, 4, 8).  The search times the streaming kernel only: where the
+ * small-grid tile kernel runs (FDW_CFG_SMALL_TILES) it keeps running after the call, with the
+ * chosen time block.  steps: time steps per candidate
  * run (0 = automatic).  best_out (host, may be NULL) receives
  * {time_block, segment_rows, lane_columns}. */
 int fdw_autotune(fdw_ctx* ctx, int32_t steps, int64_t* best_out);
