@@ -261,14 +261,14 @@ enum {
                                      4 non-temporal loads only (float); results are identical */
     FDW_CFG_SMALL_TILES = 14,     /* small-grid kernel: one workgroup per tile of 48 owned columns,
                                      its waves advancing the tile level by level together.  0 (default):
-                                     used where every member has at most 768 x 768 nodes; 1: never;
+                                     used where every member has at most 1024 x 1024 nodes; 1: never;
                                      2: wherever allowed.  Never with receiver traces or the persistent
                                      launch (the streaming kernel runs those steps).  States are
                                      identical bit for bit; energies agree to rounding (other partial
                                      sums) */
     FDW_CFG_TILE_ROWS = 15        /* rows per tile of the small-grid kernel (16 halo rows included):
-                                     32, 48 or 64 (0 = automatic: the tallest that gives a launch at
-                                     least 150 tiles, else 32) */
+                                     32, 48 or 64 (0 = automatic: 64 where that gives a launch 150 to
+                                     300 tiles, else 48 where that gives at least 150, else 32) */
 };
 int fdw_configure(fdw_ctx* ctx, int32_t key, int64_t value);
 int64_t fdw_get_config(const fdw_ctx* ctx, int32_t key);

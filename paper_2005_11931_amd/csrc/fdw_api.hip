@@ -217,21 +217,23 @@ void decompose(const fdw_ctx* c, const HostMember& hm, MemberDev& md, int S, int
     md.epart_stride = std::max(md.waves, 1);
 }
 
-// rows per tile of the small-grid kernel: the tallest tile (64, 48 or 32 rows: 16, 12 or 8
-// waves) that still gives the launch at least 150 tiles, else 32.  Measured (256^2 .. 724^2,
-// FP64 and FP32, time block 8): the per-tile time grows with the waves sharing a SIMD, the
-// redundant halo work with the tile count; about one tile per CU balances the two.
+// rows per tile of the small-grid kernel (64, 48 or 32 rows: 16, 12 or 8 waves): 64 where that
+// gives the launch 150..300 tiles (about one per CU), else 48 where that gives at least 150,
+// else 32.  Measured (256^2 .. 1024^2, FP64 and FP32, time block 8): the per-tile time grows
+// with the waves sharing a SIMD, the redundant halo work with the tile count.
 int tile_rows(const fdw_ctx* c)
 {
     if (c->tile_rows > 0) return c->tile_rows;
-    for (int rows : {64, 48}) {
+    auto tiles_of = [&](int rows) {
         int64_t tiles = 0;
         for (const HostMember& hm : c->m)
             tiles += (int64_t)((hm.nx + kTileCols - 1) / kTileCols) *
                      ((hm.ny + rows - 2 * kTileHalo - 1) / (rows - 2 * kTileHalo));
-        if (tiles >= 150) return rows;
-    }
-    return 32;
+        return tiles;
+    };
+    const int64_t t64 = tiles_of(64);
+    if (t64 >= 150 && t64 <= 300) return 64;
+    return tiles_of(48) >= 150 ? 48 : 32;
 }
 
 // The small-grid decomposition: one tile per workgroup, independent of the time block (its halo
@@ -752,9 +754,9 @@ void replay_bookkeeping(fdw_ctx* c, int64_t steps, bool persistent)
 
 // Whether a step_n call runs the small-grid tile kernel: not with receiver traces (the streaming
 // kernel records them) or the persistent launch; automatically where every member has at most
-// kTileAutoNodes nodes (there the streaming kernel's few, long work items leave most of the
-// device idle: measured faster up to 724^2, slower at 1024^2).
-constexpr int64_t kTileAutoNodes = (int64_t)768 * 768;
+// kTileAutoNodes nodes (there the streaming kernel's few, long work items leave much of the
+// device idle: measured faster from 256^2 to 1024^2 - at 1024^2 by 7% in FP64, 14% in FP32).
+constexpr int64_t kTileAutoNodes = (int64_t)1024 * 1024;
 bool want_tiles(const fdw_ctx* c)
 {
     if (c->tile_mode == 1 || c->batch_mode == 1 || any_trace(c)) return false;
