@@ -299,6 +299,14 @@ def test_small_grid_tiles_vs_streaming_and_oracle(dtype_name):
         s.close()
     assert np.array_equal(got[0][0], got[1][0]) and np.array_equal(got[0][1], got[1][1])
     assert np.abs(got[0][2] - got[1][2]).max() <= (1e-13 if dt == fdw.FDW_F64 else 1e-6) * np.abs(got[0][2]).max()
+    # configuration errors
+    s = fdw.solver_for_case(cases[1], dtype=dt)
+    for key, bad in ((fdw.FDW_CFG_SMALL_TILES, 3), (fdw.FDW_CFG_TILE_ROWS, 40), (fdw.FDW_CFG_TILE_ROWS, 16)):
+        with pytest.raises(fdw.FdwError):
+            s.configure(key, bad)
+    s.configure(fdw.FDW_CFG_TILE_ROWS, 48)
+    assert s.config(fdw.FDW_CFG_TILE_ROWS) == 48 and s.config(fdw.FDW_CFG_SMALL_TILES) == 0
+    s.close()
     # traces for one call: the streaming kernel runs those steps, the tiles the ones around them
     rec = np.array([[40, 60], [41, 60], [5, 100]], dtype=np.int32)
     ref = oracle.forward_case(cases[2], receivers=rec)
